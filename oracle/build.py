@@ -1,0 +1,28 @@
+"""Compile the FP64 CPU oracle into ``oracle/libbtrirt_oracle.so``.
+
+Test infrastructure only.  ``-ffp-contract=off`` keeps every product and sum
+rounded as written; OpenMP splits only the per-row loops (no reductions run in
+parallel), so results do not depend on the thread count.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "btrirt_oracle.c")
+LIB = os.path.join(HERE, "libbtrirt_oracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall", "-Wextra"]
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", *CFLAGS, SRC, "-o", LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
