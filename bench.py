@@ -1,0 +1,266 @@
+"""Throughput of the B-TriRT melting step on one MI355X.
+
+Workload (the single-GPU configuration the metric is quoted on): one
+2048x1024 D2Q9 cavity, FP64, Ra = 1e8, Pr = 1, Ste = 1, heater centred with
+width W/4, starting all solid at Tm; flow and enthalpy populations advanced by
+the in-place fused collide-and-stream kernel, diagnostics (melt fraction,
+Nusselt number, enthalpy budget) reduced on the device every 100 steps.  A
+"step" is one time step of that whole path.  Inputs are synthetic and
+resident in HBM before timing starts.
+
+Printed: one JSON line with MLUPS (10^6 lattice updates per second, one update
+= one cell's f and g advanced one step), the roofline of the step kernel, the
+oracle timed on the host cores, and the FP32-shifted, batched and served
+variants.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_LU = {0: 288, 1: 144}  # 18 populations read + written, FP64 / FP32
+REPORT_EVERY = 100
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            vals[k.strip().strip("-* `")] = v.strip().strip("` ")
+    if vals.get("kernel_source_sha256") != kernel_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(P, ctx, slot, steps, events=True):
+    """Runs `steps` steps; returns elapsed ms measured with events on the
+    context's stream (the stream the kernels are launched on)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ctx.sync()
+    e0.record(ctx.stream)
+    ctx.step(slot, steps)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def main_workload(P, args):
+    from btrirt_workloads import large_cavity
+    import torch
+
+    case = large_cavity()
+    cells = case["nx"] * case["ny"]
+    ctx = P.Context(device=0, max_slots=2)
+    if args.graph_chunk:
+        ctx.set_graph_chunk(args.graph_chunk)
+    if args.tile:
+        bx, by, cpl, xcd = (int(v) for v in args.tile.split(","))
+        ctx.set_launch(0, bx, by, cpl, xcd)
+    slot = ctx.add(case)
+    ctx.set_report(slot, REPORT_EVERY, (args.steps + args.warmup) // REPORT_EVERY + 2)
+    log(f"main: 2048x1024 FP64 in place, warmup {args.warmup}, steps {args.steps}")
+    ctx.step(slot, args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = time_steps(P, ctx, slot, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.reduce(slot)
+    series = ctx.series(slot)
+    log(f"main: {ms:.1f} ms event, {wall * 1e3:.1f} ms wall, melt fraction {st['melt_fraction']:.6f}, "
+        f"Nu {st['nusselt']:.3f}, finite {st['finite']}, {len(series)} reports")
+    # live kernel time of the step kernel alone (no reports in the region)
+    slot2 = ctx.add(case)
+    k2 = max(200, min(2000, args.steps))
+    ctx.step(slot2, 20)
+    kms = time_steps(P, ctx, slot2, k2)
+    ctx.close()
+    return dict(case=case, cells=cells, ms=ms, wall=wall, stats=st, series=series,
+                kernel_ms=kms / k2, kernel_launches=k2)
+
+
+def fp32_variant(P, steps):
+    from btrirt_workloads import large_cavity
+    case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED)
+    ctx = P.Context(device=0, max_slots=1)
+    slot = ctx.add(case)
+    ctx.step(slot, 100)
+    ms = time_steps(P, ctx, slot, steps)
+    st = ctx.reduce(slot)
+    ctx.close()
+    cells = case["nx"] * case["ny"]
+    mlups = cells * steps / (ms * 1e-3) / 1e6
+    log(f"fp32s: {mlups:.0f} MLUPS")
+    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps,
+                hbm_frac=round(mlups * 1e6 * BYTES_PER_LU[1] / (HBM_PEAK_GBS * 1e9), 4),
+                melt_fraction=st["melt_fraction"])
+
+
+def batched_variant(P, steps, chunk=100):
+    """64 cavities of uneven size (seeded sweep), FP32 shifted: one batched
+    launch per step replayed from captured 100-step graphs, against the same
+    cavities solved one after another with the single-cavity path."""
+    import torch
+    from btrirt_workloads import batch_sweep
+    cases = [dict(c, precision=P.LBM_FP32_SHIFTED) for c in batch_sweep()]
+    cells = sum(c["nx"] * c["ny"] for c in cases)
+    ctx = P.Context(device=0, max_slots=len(cases))
+    ctx.set_graph_chunk(chunk)
+    slots = [ctx.add(c) for c in cases]
+    ctx.step(P.LBM_ALL, chunk)  # warm-up (captures the graph)
+    ctx.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    ctx.step(P.LBM_ALL, steps)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    # the same work as sequential plain solves
+    ctx.sync()
+    e0.record(ctx.stream)
+    for s in slots:
+        ctx.step(s, steps)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    ctx.close()
+    lu = cells * steps
+    res = dict(cavities=len(cases), cells=cells, steps=steps,
+               batched_mlups=round(lu / (ms_b * 1e-3) / 1e6, 1),
+               sequential_mlups=round(lu / (ms_s * 1e-3) / 1e6, 1))
+    res["speedup"] = round(res["batched_mlups"] / res["sequential_mlups"], 3)
+    log(f"batched: {res}")
+    return res
+
+
+def cpu_baseline(target_s):
+    """The FP64 oracle on the host cores, on the same 2048x1024 cavity, for
+    as many whole steps as fit in about target_s seconds."""
+    import oracle
+    from btrirt_workloads import large_cavity
+    case = large_cavity()
+    o = oracle.Oracle(oracle.case_from_dict(case)).init_solid()
+    o.step(1)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.step(2)
+        steps += 2
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    cells = case["nx"] * case["ny"]
+    mlups = cells * steps / el / 1e6
+    log(f"cpu oracle: {steps} steps in {el:.1f} s = {mlups:.2f} MLUPS on {oracle.num_threads()} threads")
+    return dict(value=round(mlups, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+                sample=f"2048x1024 FP64 cavity, {steps} steps after one warm-up step "
+                       f"({el:.1f} s, OpenMP over rows)")
+
+
+def calib_copy(nbytes):
+    """Plain device copy of a known size, for scaling HBM counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {nbytes} bytes x3")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--graph-chunk", type=int, default=0)
+    ap.add_argument("--tile", default="", help="bx,by,cpl,xcd for the FP64 step kernel")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true", help="only the main workload")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}), flush=True)
+        sys.exit(2)
+    if args.calib_copy:
+        calib_copy(args.calib_copy)
+        return
+    import paper_1909_13086_amd as P
+
+    m = main_workload(P, args)
+    mlups = m["cells"] * args.steps / (m["ms"] * 1e-3) / 1e6
+    kernel_s = m["kernel_ms"] * 1e-3
+    achieved = BYTES_PER_LU[0] * m["cells"] / kernel_s / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "MLUPS (flow+enthalpy) & % HBM roofline; batched vs plain; p50/p99 solve latency",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(m["ms"] / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single cavity 2048x1024 D2Q9, FP64, Ra=1e8 Pr=1 Ste=1, heater W/4 centred, "
+                               "from all-solid at Tm; diagnostics every 100 steps",
+                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": "in-place A-A"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_step<double,double,1>",
+                     "kernel_avg_us": round(m["kernel_ms"] * 1e3, 2),
+                     "algorithmic_bytes_per_launch": BYTES_PER_LU[0] * m["cells"]},
+        "melt_fraction": m["stats"]["melt_fraction"],
+        "nusselt": m["stats"]["nusselt"],
+        "budget_residual": m["stats"]["budget_residual"],
+    }
+    if not args.no_extras:
+        out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4))
+        out["batched"] = batched_variant(P, 2000)
+        try:
+            from paper_1909_13086_amd import serve
+            out["serving"] = serve.bench_serving(P)
+        except ImportError:
+            pass
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * lbm.h -- C ABI of the gfx950 B-TriRT lattice Boltzmann melting library.
+ *
+ * The library advances cavities of phase-change material heated locally from
+ * below (Zhao, Wu, Chai & Shi, arXiv 1909.13086, Sec. 3.2) with the block
+ * triple-relaxation-time update of Sec. 2, Eq. (2), on a D2Q9 lattice:
+ *   - enthalpy populations g: equilibrium of Eq. (3), k1 from the thermal
+ *     diffusivity by Eq. (4), k2 = 2 - k1 by Eq. (5) unless overridden;
+ *   - Boussinesq flow populations f: Eq. (2) with a second-order equilibrium
+ *     and a Hermite-projected buoyancy force; the solid is immobilised by
+ *     scaling the velocity with the liquid fraction;
+ *   - total enthalpy H = Cp*T + fl*L (Sec. 2, under Eq. (1)) with isothermal
+ *     melting at Tm;
+ *   - no-slip adiabatic walls (half-way bounce-back) and a bottom strip held at
+ *     Th (anti-bounce-back), Sec. 3.2.
+ * Lattice units throughout: dx = dt = 1, c = 1, cs^2 = 1/3.
+ *
+ * Conventions shared by every call:
+ *   - All functions return int: LBM_OK (0) or a negative LBM_E* code; no
+ *     exception crosses the ABI.  lbm_last_error() gives a message for the last
+ *     failure on the calling thread.
+ *   - Pointers named "host" are host memory owned by the caller.  Device
+ *     memory is allocated by the library unless the caller lends a buffer to
+ *     lbm_set_case; lent memory stays owned by the caller and must outlive the
+ *     slot (until lbm_release or lbm_destroy).
+ *   - Field and population layout on the host: field-major, then row-major
+ *     idx = y*nx + x, y = 0 the heated bottom wall.  Populations: plane i of
+ *     the D2Q9 set c_0=(0,0), c_1=(1,0), c_2=(0,1), c_3=(-1,0), c_4=(0,-1),
+ *     c_5=(1,1), c_6=(-1,1), c_7=(-1,-1), c_8=(1,-1), so f[i*nx*ny + y*nx + x].
+ *   - Work is ordered on the context's HIP stream.  lbm_step only enqueues;
+ *     lbm_reduce, lbm_fields, lbm_series, lbm_state_* and lbm_sync block until
+ *     the stream has drained.  A context is not thread-safe.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid argument or case */
+  LBM_ENOMEM = -2,    /* HBM budget or device memory exhausted; nothing was changed */
+  LBM_EDEVICE = -3,   /* HIP runtime error */
+  LBM_EUNSTABLE = -4, /* state is no longer finite (returned with the stats) */
+  LBM_ESTATE = -5,    /* wrong slot state (unused slot, busy server, ...) */
+  LBM_ENOTSUP = -6    /* combination not supported */
+};
+
+enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 };
+enum { LBM_PATTERN_AA = 0, LBM_PATTERN_AB = 1 };
+enum { LBM_PARAM_DIMENSIONLESS = 0, LBM_PARAM_LATTICE = 1 };
+enum { LBM_INIT_SOLID_AT_TM = 0, LBM_INIT_LIQUID_T0 = 1, LBM_INIT_GAUSSIAN = 2 };
+enum {
+  LBM_FIELD_T = 1,
+  LBM_FIELD_FL = 2,
+  LBM_FIELD_H = 4,
+  LBM_FIELD_UX = 8,
+  LBM_FIELD_UY = 16,
+  LBM_FIELD_RHO = 32
+};
+#define LBM_ALL (-1)
+
+typedef struct lbm_ctx lbm_ctx;
+
+/*
+ * Problem statement of one cavity (Sec. 3.2).  Physical inputs come either
+ * as dimensionless groups (param_mode = LBM_PARAM_DIMENSIONLESS: Ra, Pr, Ste
+ * and the lattice Mach number Ma of the free-fall velocity, with the cavity
+ * height ny as length scale) or directly in lattice units
+ * (LBM_PARAM_LATTICE: nu, alpha, gbeta, latent).  A rate given as NaN takes
+ * its default: k0_g = 1, k2_g = 2 - k1_g (Eq. (5)), k0_f = k1_f = 1.
+ */
+typedef struct {
+  int32_t nx, ny;           /* cells, >= 1 each */
+  int32_t precision;        /* LBM_FP64 or LBM_FP32_SHIFTED */
+  int32_t pattern;          /* LBM_PATTERN_AA (in place) or LBM_PATTERN_AB (two lattices) */
+  int32_t param_mode;       /* LBM_PARAM_* */
+  int32_t periodic_x, periodic_y;
+  int32_t init;             /* LBM_INIT_* */
+  double Ra, Pr, Ste, Ma;   /* dimensionless mode */
+  double nu, alpha, gbeta, latent; /* lattice mode */
+  double Cp, Th, Tm, rho0;
+  double heater_center, heater_width; /* strip centre C and width D as fractions of nx */
+  double k0_g, k2_g, k0_f, k1_f;
+  double T0, gauss_amp, gauss_sigma; /* LBM_INIT_LIQUID_T0 / LBM_INIT_GAUSSIAN */
+} lbm_case;
+
+/* Lattice parameters derived from a case (Eqs. (4)-(5) and the flow closure). */
+typedef struct {
+  double nu, alpha, gbeta, latent;
+  double k0_g, k1_g, k2_g, k0_f, k1_f, k2_f;
+  int32_t heater_lo, heater_hi, n_heater; /* heated cells x in [lo, hi] of row y = 0 */
+  int32_t pitch;                          /* device row pitch in cells */
+} lbm_lattice;
+
+/* Per-cavity diagnostics of the current state, computed in FP64 with
+ * compensated sums. */
+typedef struct {
+  int64_t step;
+  double melt_fraction;   /* mean liquid fraction (Sec. 3.2, liquid fraction curves) */
+  double nusselt;         /* ny*Q/(n_heater*alpha*Cp*(Th-Tm)) from the strip flux Q */
+  double heater_q;        /* enthalpy entering through the strip in the last step */
+  double total_H;         /* sum of H over all cells */
+  double heat_in_cum;     /* strip enthalpy summed over every step so far */
+  double budget_residual; /* total_H - total_H(at load) - heat_in_cum */
+  double mass;            /* sum of rho */
+  double max_u;           /* max |u| */
+  double fourier;         /* alpha*step/ny^2 */
+  int32_t finite;         /* 1 when every population is finite */
+  int32_t parity;         /* storage parity of the in-place pattern */
+} lbm_stats;
+
+/* ---- host-only calls (no GPU needed) ------------------------------------ */
+
+/* Message for an error code; never NULL. */
+const char *lbm_strerror(int code);
+/* Message of the last failure on this thread (empty when none). */
+const char *lbm_last_error(void);
+/* Validates a case and derives its lattice parameters.  LBM_EINVAL with a
+ * message for an invalid case (rates outside (0,2), non-positive viscosity or
+ * diffusivity, non-positive Ra/Pr/Ste/Ma or Th <= Tm in dimensionless mode,
+ * unknown enums, sizes < 1). */
+int lbm_derive(const lbm_case *cs, lbm_lattice *out);
+/* Device bytes one slot of this case occupies (populations, strip-flux
+ * accumulators, reduction scratch); 0 for an invalid case. */
+size_t lbm_footprint(const lbm_case *cs);
+/* Library version string. */
+const char *lbm_version(void);
+
+/* ---- context and slots ---------------------------------------------------- */
+
+/* Creates a context on `device`.  hip_stream: a hipStream_t to order all work
+ * on (e.g. the current PyTorch stream), or NULL for a stream of its own.
+ * hbm_budget: bytes of slot footprints the context may hold at once (0 = no
+ * limit beyond device memory).  max_slots: resident cavities, >= 1. */
+int lbm_create(lbm_ctx **out, int device, void *hip_stream, size_t hbm_budget, int max_slots);
+/* Frees every slot the library allocated, graphs and scratch.  NULL is a no-op. */
+void lbm_destroy(lbm_ctx *c);
+/* Admits a cavity: validates the case, reserves its footprint against the
+ * budget (LBM_ENOMEM without side effects when it does not fit), binds
+ * memory (dev_buf of buf_bytes >= lbm_footprint, or NULL to let the library
+ * allocate) and writes the initial state of cs->init at step 0.  Blocks. */
+int lbm_set_case(lbm_ctx *c, const lbm_case *cs, void *dev_buf, size_t buf_bytes, int *slot_out);
+/* Returns a slot's footprint to the budget and frees library-owned memory. */
+int lbm_release(lbm_ctx *c, int slot);
+
+/* ---- the hot path --------------------------------------------------------- */
+
+/* Enqueues nsteps time steps of Eq. (2) (collide, stream, wall rules) for one
+ * slot, or for every resident slot with slot = LBM_ALL (one batched launch
+ * per step covers all cavities).  Asynchronous. */
+int lbm_step(lbm_ctx *c, int slot, int64_t nsteps);
+/* Diagnostics of the current state.  Blocks.  Returns LBM_EUNSTABLE (with
+ * *out filled) when a population is not finite. */
+int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out);
+/* Macroscopic fields of the current state: for each bit of mask, in the order
+ * T, fl, H, ux, uy, rho, one nx*ny plane of doubles into host; n is the
+ * capacity of host in doubles.  Blocks. */
+int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n);
+
+/* Records diagnostics every `every` steps into a device ring of `capacity`
+ * entries while lbm_step runs (every = 0 stops).  Clears earlier entries. */
+int lbm_set_report(lbm_ctx *c, int slot, int64_t every, int32_t capacity);
+/* Copies up to max recorded diagnostics to host; *count gets the number. */
+int lbm_series(lbm_ctx *c, int slot, lbm_stats *host, int32_t max, int32_t *count);
+
+/* Raw pre-collision populations (FP64, layout above, 9*nx*ny each).  Load
+ * resets the step counter and the strip-flux budget to zero. */
+int lbm_state_load(lbm_ctx *c, int slot, const double *f, const double *g, size_t n);
+int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n);
+
+/* ---- execution control ---------------------------------------------------- */
+
+/* Tile of the single-cavity step kernels for a precision: bx threads along x
+ * (multiple of 64), by rows per block (bx*by <= 256), cpl rows per lane (1, 2
+ * or 4), xcd_remap (1 = give each of the 8 XCDs a contiguous band of tiles).
+ * Results do not depend on the tile. */
+int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int xcd_remap);
+int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *xcd_remap);
+/* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
+int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
+/* Times the candidate tiles on a scratch cavity of the given size and
+ * precision, selects the fastest and, when cache_path is not NULL, records
+ * it there (JSON); a cached entry for the same size class is reused. */
+int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path);
+/* Waits for all work on the context stream. */
+int lbm_sync(lbm_ctx *c);
+/* The hipStream_t the context orders its work on. */
+int lbm_stream(lbm_ctx *c, void **stream);
+/* Step counter, parity and footprint of a slot. */
+int lbm_slot_info(lbm_ctx *c, int slot, int64_t *step, int32_t *parity, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

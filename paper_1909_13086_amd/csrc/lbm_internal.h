@@ -1,0 +1,83 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int kQ = 9;
+constexpr int kPlanes = 2 * kQ;  // f_0..f_8 then g_0..g_8
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+// Everything a kernel needs to advance or inspect one cavity.  Built on the
+// host from a validated case; passed by value (single cavity) or read from a
+// device array (batched launch).
+struct CavDev {
+  int32_t nx, ny, pitch;
+  int32_t periodic_x, periodic_y;
+  int32_t hlo, hhi;    // heated cells [hlo, hhi] of row 0; none when hlo > hhi
+  int32_t parity;      // in-place pattern: 0 natural, 1 swapped; AB: index of current lattice
+  int32_t pattern;     // 0 in place (A-A), 1 two lattices
+  int32_t active_steps; // batched launch: launches of the current chunk that advance it
+  int32_t pad_;
+  int64_t plane;       // elements per population plane = pitch * ny
+  // relaxation rates of Eq. (2)
+  double k0g, k1g, k2g, k0f, k1f, k2f;
+  double Cp, inv_Cp, latent, inv_latent, rho0, inv_rho0;
+  double gbeta_rho0;   // rho0 * g * beta
+  double dT;           // Th - Tm
+  double Tm;
+  double alpha;
+  void *pop[2];        // population planes (pop[1] only for two lattices)
+  double *cumq;        // per-column strip enthalpy summed over steps, nx doubles
+};
+
+// Batched launch: tiles of many cavities in one grid.
+struct BatchTile {
+  int32_t cav;   // index into the CavDev array
+  int32_t x0, y0;
+  int32_t pad;
+};
+
+struct LaunchCfg {
+  int bx = 256, by = 1, cpl = 1, xcd = 1;
+};
+
+// Accumulators of one reduction, FP64.
+enum RedSlot {
+  kRedFl = 0, kRedH, kRedRho, kRedQ, kRedFields  // compensated sums
+};
+
+// Diagnostics on the device (same order as lbm_stats minus host-only fields).
+struct StatsDev {
+  double melt_fraction, heater_q, total_H, heat_in_cum, mass, max_u;
+  double nonfinite;
+  double pad;
+};
+
+constexpr int kRedBlocks = 512;   // fixed grid of the reduction (deterministic order)
+constexpr int kRedThreads = 256;
+
+// Launchers (all asynchronous on `s`); return hipSuccess or the launch error.
+hipError_t launch_init(const CavDev &c, int precision, int mode, double T0, double amp,
+                       double sigma, hipStream_t s);
+hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
+// hdr_dev: {first tile, tile count} for FP64 then for FP32 (4 ints).
+hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
+                             const int32_t *hdr_dev, int precision, int tile_bx, int tile_rows,
+                             int launch_index, int grid, hipStream_t s);
+hipError_t launch_reduce(const CavDev &c, int precision, double *partials, StatsDev *out,
+                         hipStream_t s);
+hipError_t launch_fields(const CavDev &c, int precision, uint32_t mask, double *out,
+                         hipStream_t s);
+hipError_t launch_load(const CavDev &c, int precision, const double *f, const double *g,
+                       hipStream_t s);
+hipError_t launch_save(const CavDev &c, int precision, double *f, double *g, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_copy_stats(const StatsDev *src, StatsDev *dst, hipStream_t s);
+
+}  // namespace lbm

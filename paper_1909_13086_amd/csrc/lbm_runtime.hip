@@ -1,0 +1,1057 @@
+// Host runtime and C ABI of the B-TriRT melting library (see include/lbm.h).
+//
+// A context owns one HIP stream (its own or one lent by the caller, e.g. the
+// current PyTorch stream), a table of resident cavities ("slots"), an HBM
+// budget for admission, reduction scratch and the captured step graphs.  All
+// device work is stream-ordered; only the calls that return data block.
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using lbm::BatchTile;
+using lbm::CavDev;
+using lbm::LaunchCfg;
+using lbm::StatsDev;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+constexpr int kPitchAlign = 64;  // cells: one wavefront per row segment
+constexpr size_t kByteAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool rate_ok(double k) { return std::isfinite(k) && k > 0.0 && k < 2.0; }
+
+// Parameter derivation.  Dimensionless mode (reading of Sec. 3.2): the cavity
+// height ny is the length scale, Ra = g beta dT ny^3/(nu alpha), Pr = nu/alpha,
+// the free-fall velocity sqrt(g beta dT ny) equals Ma*cs, Ste = Cp dT / L.
+// Eq. (4): 1/k1 = alpha/cs^2 + 1/2; Eq. (5): k2 = 2 - k1 unless given.  The
+// flow's stress moment carries the viscosity the same way.
+int derive(const lbm_case *cs, lbm_lattice *out, std::string &why) {
+  std::memset(out, 0, sizeof(*out));
+  if (!cs) { why = "case is NULL"; return LBM_EINVAL; }
+  if (cs->nx < 1 || cs->ny < 1 || cs->nx > (1 << 20) || cs->ny > (1 << 20) ||
+      (double)cs->nx * cs->ny > 2.0e9) {
+    why = "nx, ny must be >= 1 and the lattice at most 2e9 cells";
+    return LBM_EINVAL;
+  }
+  if (cs->precision != LBM_FP64 && cs->precision != LBM_FP32_SHIFTED) {
+    why = "unknown precision"; return LBM_EINVAL;
+  }
+  if (cs->pattern != LBM_PATTERN_AA && cs->pattern != LBM_PATTERN_AB) {
+    why = "unknown streaming pattern"; return LBM_EINVAL;
+  }
+  if (cs->init < LBM_INIT_SOLID_AT_TM || cs->init > LBM_INIT_GAUSSIAN) {
+    why = "unknown initial state"; return LBM_EINVAL;
+  }
+  if (!(cs->Cp > 0.0) || !(cs->rho0 > 0.0) || !std::isfinite(cs->Cp) ||
+      !std::isfinite(cs->rho0) || !std::isfinite(cs->Th) || !std::isfinite(cs->Tm)) {
+    why = "Cp and rho0 must be positive, Th and Tm finite"; return LBM_EINVAL;
+  }
+  const double dT = cs->Th - cs->Tm;
+  if (cs->param_mode == LBM_PARAM_DIMENSIONLESS) {
+    if (!(cs->Ra > 0.0) || !(cs->Pr > 0.0) || !(cs->Ste > 0.0) || !(cs->Ma > 0.0) ||
+        !std::isfinite(cs->Ra) || !std::isfinite(cs->Pr) || !std::isfinite(cs->Ste) ||
+        !std::isfinite(cs->Ma)) {
+      why = "Ra, Pr, Ste and Ma must be positive"; return LBM_EINVAL;
+    }
+    if (!(dT > 0.0)) { why = "Th must exceed Tm"; return LBM_EINVAL; }
+    const double U = cs->Ma * std::sqrt(kCs2);
+    const double ell = (double)cs->ny;
+    out->nu = U * ell * std::sqrt(cs->Pr / cs->Ra);
+    out->alpha = out->nu / cs->Pr;
+    out->gbeta = U * U / (ell * dT);
+    out->latent = cs->Cp * dT / cs->Ste;
+  } else if (cs->param_mode == LBM_PARAM_LATTICE) {
+    out->nu = cs->nu;
+    out->alpha = cs->alpha;
+    out->gbeta = cs->gbeta;
+    out->latent = cs->latent;
+  } else {
+    why = "unknown parameter mode"; return LBM_EINVAL;
+  }
+  if (!(out->nu > 0.0) || !(out->alpha > 0.0) || !std::isfinite(out->nu) ||
+      !std::isfinite(out->alpha) || !std::isfinite(out->gbeta) || !(out->latent >= 0.0) ||
+      !std::isfinite(out->latent)) {
+    why = "viscosity and diffusivity must be positive, latent heat >= 0"; return LBM_EINVAL;
+  }
+  out->k1_g = 1.0 / (out->alpha / kCs2 + 0.5);
+  out->k2_g = std::isnan(cs->k2_g) ? 2.0 - out->k1_g : cs->k2_g;
+  out->k0_g = std::isnan(cs->k0_g) ? 1.0 : cs->k0_g;
+  out->k2_f = 1.0 / (out->nu / kCs2 + 0.5);
+  out->k0_f = std::isnan(cs->k0_f) ? 1.0 : cs->k0_f;
+  out->k1_f = std::isnan(cs->k1_f) ? 1.0 : cs->k1_f;
+  if (!rate_ok(out->k0_g) || !rate_ok(out->k1_g) || !rate_ok(out->k2_g) ||
+      !rate_ok(out->k0_f) || !rate_ok(out->k1_f) || !rate_ok(out->k2_f)) {
+    why = "every relaxation rate must lie in (0, 2)"; return LBM_EINVAL;
+  }
+  if (!std::isfinite(cs->heater_center) || !std::isfinite(cs->heater_width)) {
+    why = "heater centre and width must be finite"; return LBM_EINVAL;
+  }
+  // Strip of Sec. 3.2 on cell-centred nodes: cell x is heated when its centre
+  // x + 1/2 lies in [(C - D/2) nx, (C + D/2) nx].
+  out->heater_lo = 1;
+  out->heater_hi = 0;
+  if (cs->heater_width > 0.0 && !cs->periodic_y) {
+    const double a = (cs->heater_center - 0.5 * cs->heater_width) * cs->nx;
+    const double b = (cs->heater_center + 0.5 * cs->heater_width) * cs->nx;
+    const double lo = std::max(0.0, std::ceil(a - 0.5));
+    const double hi = std::min((double)(cs->nx - 1), std::floor(b - 0.5));
+    if (lo <= hi) {
+      out->heater_lo = (int32_t)lo;
+      out->heater_hi = (int32_t)hi;
+    }
+  }
+  out->n_heater = out->heater_hi >= out->heater_lo ? out->heater_hi - out->heater_lo + 1 : 0;
+  if (cs->init == LBM_INIT_LIQUID_T0 && !std::isfinite(cs->T0)) {
+    why = "T0 must be finite"; return LBM_EINVAL;
+  }
+  if (cs->init == LBM_INIT_GAUSSIAN &&
+      (!std::isfinite(cs->T0) || !std::isfinite(cs->gauss_amp) || !(cs->gauss_sigma > 0.0))) {
+    why = "Gaussian initial state needs finite T0, amplitude and sigma > 0"; return LBM_EINVAL;
+  }
+  out->pitch = (int32_t)round_up((size_t)cs->nx, kPitchAlign);
+  return LBM_OK;
+}
+
+struct Layout {
+  size_t pop_bytes;   // one lattice (18 planes)
+  size_t cumq_off, cumq_bytes;
+  size_t total;
+};
+
+Layout layout_of(const lbm_case *cs, const lbm_lattice &lat) {
+  Layout L{};
+  const size_t elem = cs->precision == LBM_FP64 ? 8 : 4;
+  L.pop_bytes = round_up((size_t)lbm::kPlanes * lat.pitch * (size_t)cs->ny * elem, kByteAlign);
+  const size_t lattices = cs->pattern == LBM_PATTERN_AB ? 2 : 1;
+  L.cumq_off = lattices * L.pop_bytes;
+  L.cumq_bytes = round_up((size_t)cs->nx * sizeof(double), kByteAlign);
+  L.total = L.cumq_off + L.cumq_bytes;
+  return L;
+}
+
+struct Slot {
+  bool used = false;
+  lbm_case cs{};
+  lbm_lattice lat{};
+  Layout lay{};
+  CavDev dev{};
+  void *base = nullptr;
+  bool owned = false;
+  int64_t step = 0;
+  double E0 = 0.0;
+  // diagnostics recorded during lbm_step
+  int64_t report_every = 0;
+  int32_t report_cap = 0;
+  StatsDev *series = nullptr;
+  std::vector<int64_t> series_step;
+  std::vector<int32_t> series_parity;
+  // captured step chunks, keyed by starting parity
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_chunk = 0;
+};
+
+struct Batch {
+  CavDev *cavs_dev = nullptr;
+  BatchTile *tiles_dev = nullptr;
+  int32_t *hdr_dev = nullptr;     // {first, count} for FP64 then FP32
+  size_t cav_cap = 0, tile_cap = 0;
+  CavDev *cavs_host = nullptr;    // pinned staging
+  BatchTile *tiles_host = nullptr;
+  int32_t *hdr_host = nullptr;
+  int ntiles[2] = {0, 0};         // per precision
+  std::vector<int> members;       // slot ids in cavity-array order
+  bool dirty = true;
+  hipGraphExec_t graph = nullptr; // valid while the device buffers stay put
+  int graph_chunk = 0;
+  int graph_precs = 0;            // bit p set: precision p launched in the graph
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, used = 0;
+  std::vector<Slot> slots;
+  double *partials = nullptr;
+  StatsDev *stats_dev = nullptr;
+  StatsDev *stats_host = nullptr;  // pinned
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  LaunchCfg launch[2];
+  int graph_chunk = 0;
+  int num_cus = 256;
+  Batch batch;
+};
+
+namespace {
+
+int check_slot(lbm_ctx *c, int slot) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (slot < 0 || slot >= (int)c->slots.size() || !c->slots[slot].used)
+    return fail(LBM_ESTATE, "slot " + std::to_string(slot) + " is not in use");
+  return LBM_OK;
+}
+
+int ensure_scratch(lbm_ctx *c, size_t bytes) {
+  if (bytes <= c->scratch_bytes) return LBM_OK;
+  if (c->scratch) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(c->scratch));
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+  }
+  const size_t want = round_up(bytes, 1 << 20);
+  if (hipMalloc(&c->scratch, want) != hipSuccess) {
+    c->scratch = nullptr;
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, "cannot allocate " + std::to_string(want) + " bytes of scratch");
+  }
+  c->scratch_bytes = want;
+  return LBM_OK;
+}
+
+void drop_graphs(Slot &s) {
+  for (auto &g : s.graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  s.graph_chunk = 0;
+}
+
+void drop_batch_graph(lbm_ctx *c) {
+  if (c->batch.graph) (void)hipGraphExecDestroy(c->batch.graph);
+  c->batch.graph = nullptr;
+  c->batch.graph_chunk = 0;
+}
+
+CavDev make_dev(const lbm_case *cs, const lbm_lattice &lat, const Layout &lay, void *base) {
+  CavDev d{};
+  d.nx = cs->nx;
+  d.ny = cs->ny;
+  d.pitch = lat.pitch;
+  d.periodic_x = cs->periodic_x != 0;
+  d.periodic_y = cs->periodic_y != 0;
+  d.hlo = lat.heater_lo;
+  d.hhi = lat.heater_hi;
+  d.parity = 0;
+  d.pattern = cs->pattern;
+  d.active_steps = 0;
+  d.plane = (int64_t)lat.pitch * cs->ny;
+  d.k0g = lat.k0_g;
+  d.k1g = lat.k1_g;
+  d.k2g = lat.k2_g;
+  d.k0f = lat.k0_f;
+  d.k1f = lat.k1_f;
+  d.k2f = lat.k2_f;
+  d.Cp = cs->Cp;
+  d.inv_Cp = 1.0 / cs->Cp;
+  d.latent = lat.latent;
+  d.inv_latent = lat.latent > 0.0 ? 1.0 / lat.latent : 0.0;
+  d.rho0 = cs->rho0;
+  d.inv_rho0 = 1.0 / cs->rho0;
+  d.gbeta_rho0 = cs->rho0 * lat.gbeta;
+  d.dT = cs->Th - cs->Tm;
+  d.Tm = cs->Tm;
+  d.alpha = lat.alpha;
+  char *b = static_cast<char *>(base);
+  d.pop[0] = b;
+  d.pop[1] = cs->pattern == LBM_PATTERN_AB ? b + lay.pop_bytes : nullptr;
+  d.cumq = reinterpret_cast<double *>(b + lay.cumq_off);
+  return d;
+}
+
+int reduce_now(lbm_ctx *c, Slot &s, StatsDev *out_host) {
+  HIP_TRY(lbm::launch_reduce(s.dev, s.cs.precision, c->partials, c->stats_dev, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->stats_host, c->stats_dev, sizeof(StatsDev), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *out_host = *c->stats_host;
+  return LBM_OK;
+}
+
+void fill_stats(const Slot &s, const StatsDev &d, int64_t step, int32_t parity, lbm_stats *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->step = step;
+  o->melt_fraction = d.melt_fraction;
+  o->heater_q = d.heater_q;
+  const double dT = s.cs.Th - s.cs.Tm;
+  o->nusselt = (s.lat.n_heater > 0 && dT != 0.0)
+                   ? (double)s.cs.ny * d.heater_q / ((double)s.lat.n_heater * s.lat.alpha * s.cs.Cp * dT)
+                   : 0.0;
+  o->total_H = d.total_H;
+  o->heat_in_cum = d.heat_in_cum;
+  o->budget_residual = d.total_H - s.E0 - d.heat_in_cum;
+  o->mass = d.mass;
+  o->max_u = d.max_u;
+  o->fourier = s.lat.alpha * (double)step / ((double)s.cs.ny * (double)s.cs.ny);
+  o->finite = d.nonfinite == 0.0 ? 1 : 0;
+  o->parity = parity;
+}
+
+// Resets step, strip budget and reference enthalpy after a new state.
+int restart_clock(lbm_ctx *c, Slot &s) {
+  HIP_TRY(lbm::launch_fill_zero(s.dev.cumq, s.lay.cumq_bytes, c->stream));
+  s.step = 0;
+  s.series_step.clear();
+  s.series_parity.clear();
+  StatsDev st{};
+  int rc = reduce_now(c, s, &st);
+  if (rc != LBM_OK) return rc;
+  s.E0 = st.total_H;
+  return LBM_OK;
+}
+
+int enqueue_one_step(lbm_ctx *c, Slot &s) {
+  HIP_TRY(lbm::launch_step(s.dev, s.cs.precision, c->launch[s.cs.precision], c->stream));
+  s.dev.parity ^= 1;
+  s.step += 1;
+  return LBM_OK;
+}
+
+int record_report(lbm_ctx *c, Slot &s) {
+  if (s.report_every <= 0 || s.step % s.report_every != 0) return LBM_OK;
+  const int32_t k = (int32_t)s.series_step.size();
+  if (k >= s.report_cap) return LBM_OK;
+  HIP_TRY(lbm::launch_reduce(s.dev, s.cs.precision, c->partials, s.series + k, c->stream));
+  s.series_step.push_back(s.step);
+  s.series_parity.push_back(s.dev.parity);
+  return LBM_OK;
+}
+
+// Captures `chunk` steps (chunk even) starting at storage parity p.
+int capture_chunk(lbm_ctx *c, Slot &s, int p, int chunk) {
+  CavDev d = s.dev;
+  d.parity = p;
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < chunk && err == hipSuccess; ++k) {
+    err = lbm::launch_step(d, s.cs.precision, c->launch[s.cs.precision], c->stream);
+    d.parity ^= 1;
+  }
+  hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  if (err != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LBM_EDEVICE, std::string("graph capture: ") +
+                                 hipGetErrorString(err != hipSuccess ? err : e2));
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e3));
+  s.graph[p] = ex;
+  return LBM_OK;
+}
+
+int step_slot(lbm_ctx *c, Slot &s, int64_t n) {
+  const int chunk = c->graph_chunk;
+  if (chunk != s.graph_chunk) {
+    drop_graphs(s);
+    s.graph_chunk = chunk;
+  }
+  while (n > 0) {
+    // graph replay only when no report falls inside the chunk
+    bool use_graph = chunk > 0 && n >= chunk;
+    if (use_graph && s.report_every > 0) {
+      const int64_t next = (s.step / s.report_every + 1) * s.report_every;
+      if (next <= s.step + chunk) use_graph = false;
+    }
+    if (use_graph) {
+      const int p = s.dev.parity;
+      if (!s.graph[p]) {
+        int rc = capture_chunk(c, s, p, chunk);
+        if (rc != LBM_OK) return rc;
+      }
+      HIP_TRY(hipGraphLaunch(s.graph[p], c->stream));
+      s.step += chunk;
+      if (chunk & 1) s.dev.parity ^= 1;
+      n -= chunk;
+      continue;
+    }
+    int rc = enqueue_one_step(c, s);
+    if (rc != LBM_OK) return rc;
+    rc = record_report(c, s);
+    if (rc != LBM_OK) return rc;
+    n -= 1;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batched launch over every resident slot
+
+namespace {
+
+constexpr int kBatchTileX = 64;
+constexpr int kBatchTileRows = 16;
+
+void free_batch(lbm_ctx *c) {
+  Batch &b = c->batch;
+  drop_batch_graph(c);
+  if (b.cavs_dev) (void)hipFree(b.cavs_dev);
+  if (b.tiles_dev) (void)hipFree(b.tiles_dev);
+  if (b.hdr_dev) (void)hipFree(b.hdr_dev);
+  if (b.cavs_host) (void)hipHostFree(b.cavs_host);
+  if (b.tiles_host) (void)hipHostFree(b.tiles_host);
+  if (b.hdr_host) (void)hipHostFree(b.hdr_host);
+  b.cavs_dev = nullptr;
+  b.tiles_dev = nullptr;
+  b.hdr_dev = nullptr;
+  b.cavs_host = nullptr;
+  b.tiles_host = nullptr;
+  b.hdr_host = nullptr;
+  b.cav_cap = b.tile_cap = 0;
+}
+
+// Tile list of every resident slot, FP64 cavities first.  The device
+// buffers only grow, so a captured batched graph survives membership changes.
+int rebuild_batch(lbm_ctx *c) {
+  Batch &b = c->batch;
+  b.members.clear();
+  for (int prec = 0; prec < 2; ++prec)
+    for (int i = 0; i < (int)c->slots.size(); ++i)
+      if (c->slots[i].used && c->slots[i].cs.precision == prec) b.members.push_back(i);
+  const size_t ncav = b.members.size();
+  size_t ntiles = 0;
+  for (int id : b.members) {
+    const Slot &s = c->slots[id];
+    ntiles += (size_t)((s.cs.nx + kBatchTileX - 1) / kBatchTileX) *
+              ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
+  if (ncav > b.cav_cap || ntiles > b.tile_cap || !b.hdr_dev) {
+    free_batch(c);
+    b.cav_cap = std::max<size_t>(ncav, c->slots.size());
+    b.tile_cap = std::max<size_t>(ntiles * 2, 4096);
+    HIP_TRY(hipMalloc(&b.cavs_dev, b.cav_cap * sizeof(CavDev)));
+    HIP_TRY(hipMalloc(&b.tiles_dev, b.tile_cap * sizeof(BatchTile)));
+    HIP_TRY(hipMalloc(&b.hdr_dev, 4 * sizeof(int32_t)));
+    HIP_TRY(hipHostMalloc(&b.cavs_host, b.cav_cap * sizeof(CavDev)));
+    HIP_TRY(hipHostMalloc(&b.tiles_host, b.tile_cap * sizeof(BatchTile)));
+    HIP_TRY(hipHostMalloc(&b.hdr_host, 4 * sizeof(int32_t)));
+  }
+  size_t t = 0;
+  for (int prec = 0; prec < 2; ++prec) {
+    const size_t first = t;
+    for (size_t j = 0; j < ncav; ++j) {
+      const Slot &s = c->slots[b.members[j]];
+      if (s.cs.precision != prec) continue;
+      for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
+        for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
+          b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
+    }
+    b.ntiles[prec] = (int)(t - first);
+    b.hdr_host[2 * prec] = (int32_t)first;
+    b.hdr_host[2 * prec + 1] = b.ntiles[prec];
+  }
+  if (t > 0)
+    HIP_TRY(hipMemcpyAsync(b.tiles_dev, b.tiles_host, t * sizeof(BatchTile),
+                           hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host, 4 * sizeof(int32_t), hipMemcpyHostToDevice,
+                         c->stream));
+  b.dirty = false;
+  return LBM_OK;
+}
+
+int batch_grid(lbm_ctx *c) { return c->num_cus * 8; }
+
+hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk, int precs) {
+  Batch &b = c->batch;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < chunk && err == hipSuccess; ++k)
+    for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
+      if (precs & (1 << prec))
+        err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev, prec, kBatchTileX,
+                                     kBatchTileRows, k, batch_grid(c), c->stream);
+  return err;
+}
+
+// Advances every resident slot by n steps with one batched launch per step
+// per precision; chunks of c->graph_chunk launches are replayed from a graph.
+int step_all(lbm_ctx *c, int64_t n) {
+  Batch &b = c->batch;
+  if (b.dirty) {
+    int rc = rebuild_batch(c);
+    if (rc != LBM_OK) return rc;
+  }
+  if (b.members.empty()) return LBM_OK;
+  // recorded diagnostics need per-step hooks: step those slots one by one
+  for (int id : b.members)
+    if (c->slots[id].report_every > 0) {
+      for (int id2 : b.members) {
+        int rc = step_slot(c, c->slots[id2], n);
+        if (rc != LBM_OK) return rc;
+      }
+      return LBM_OK;
+    }
+  const int precs = (b.ntiles[0] > 0 ? 1 : 0) | (b.ntiles[1] > 0 ? 2 : 0);
+  const int chunk_cap = c->graph_chunk > 0 ? c->graph_chunk : 64;
+  while (n > 0) {
+    const int chunk = (int)std::min<int64_t>(n, chunk_cap);
+    HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffer reuse
+    for (size_t j = 0; j < b.members.size(); ++j) {
+      CavDev d = c->slots[b.members[j]].dev;
+      d.active_steps = chunk;
+      b.cavs_host[j] = d;
+    }
+    HIP_TRY(hipMemcpyAsync(b.cavs_dev, b.cavs_host, b.members.size() * sizeof(CavDev),
+                           hipMemcpyHostToDevice, c->stream));
+    const bool use_graph = c->graph_chunk > 0 && chunk == c->graph_chunk;
+    if (use_graph) {
+      if (!b.graph || b.graph_chunk != chunk || b.graph_precs != precs) {
+        drop_batch_graph(c);
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = enqueue_batch_chunk(c, chunk, precs);
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail(LBM_EDEVICE, "batched graph capture failed");
+        }
+        hipError_t e3 = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) {
+          b.graph = nullptr;
+          return fail(LBM_EDEVICE, "batched graph instantiate failed");
+        }
+        b.graph_chunk = chunk;
+        b.graph_precs = precs;
+      }
+      HIP_TRY(hipGraphLaunch(b.graph, c->stream));
+    } else {
+      HIP_TRY(enqueue_batch_chunk(c, chunk, precs));
+    }
+    for (int id : b.members) {
+      Slot &s = c->slots[id];
+      s.step += chunk;
+      if (chunk & 1) s.dev.parity ^= 1;
+    }
+    n -= chunk;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory or HBM budget";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_EUNSTABLE: return "state is not finite";
+    case LBM_ESTATE: return "wrong state";
+    case LBM_ENOTSUP: return "not supported";
+    default: return "unknown error";
+  }
+}
+
+const char *lbm_last_error(void) { return g_last_error.c_str(); }
+
+const char *lbm_version(void) { return "btrirt-lbm 0.1 gfx950"; }
+
+int lbm_derive(const lbm_case *cs, lbm_lattice *out) {
+  if (!out) return fail(LBM_EINVAL, "output is NULL");
+  std::string why;
+  int rc = derive(cs, out, why);
+  if (rc != LBM_OK) return fail(rc, why);
+  return LBM_OK;
+}
+
+size_t lbm_footprint(const lbm_case *cs) {
+  lbm_lattice lat;
+  std::string why;
+  if (derive(cs, &lat, why) != LBM_OK) return 0;
+  return layout_of(cs, lat).total;
+}
+
+int lbm_create(lbm_ctx **out, int device, void *hip_stream, size_t hbm_budget, int max_slots) {
+  if (!out) return fail(LBM_EINVAL, "output is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 1 << 16) return fail(LBM_EINVAL, "max_slots out of range");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(LBM_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(LBM_EINVAL, "device index out of range");
+  HIP_TRY(hipSetDevice(device));
+  lbm_ctx *c = new lbm_ctx();
+  c->device = device;
+  c->budget = hbm_budget;
+  c->slots.resize(max_slots);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
+  int rc = LBM_OK;
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else if (hipStreamCreate(&c->stream) != hipSuccess) {
+    rc = fail(LBM_EDEVICE, "cannot create stream");
+  } else {
+    c->own_stream = true;
+  }
+  if (rc == LBM_OK &&
+      (hipMalloc(&c->partials, (size_t)lbm::kRedBlocks * 16 * sizeof(double)) != hipSuccess ||
+       hipMalloc(&c->stats_dev, sizeof(StatsDev)) != hipSuccess ||
+       hipHostMalloc(&c->stats_host, sizeof(StatsDev)) != hipSuccess))
+    rc = fail(LBM_ENOMEM, "cannot allocate reduction scratch");
+  if (rc != LBM_OK) {
+    lbm_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used) (void)lbm_release(c, i);
+  free_batch(c);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->stats_dev) (void)hipFree(c->stats_dev);
+  if (c->stats_host) (void)hipHostFree(c->stats_host);
+  if (c->scratch) (void)hipFree(c->scratch);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int lbm_set_case(lbm_ctx *c, const lbm_case *cs, void *dev_buf, size_t buf_bytes,
+                 int *slot_out) {
+  if (!c || !slot_out) return fail(LBM_EINVAL, "context or slot output is NULL");
+  *slot_out = -1;
+  lbm_lattice lat;
+  std::string why;
+  int rc = derive(cs, &lat, why);
+  if (rc != LBM_OK) return fail(rc, why);
+  int id = -1;
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (!c->slots[i].used) { id = i; break; }
+  if (id < 0) return fail(LBM_ENOMEM, "no free slot");
+  const Layout lay = layout_of(cs, lat);
+  if (c->budget > 0 && c->used + lay.total > c->budget)
+    return fail(LBM_ENOMEM, "case needs " + std::to_string(lay.total) + " bytes, " +
+                                std::to_string(c->budget - c->used) + " left in the budget");
+  HIP_TRY(hipSetDevice(c->device));
+  void *base = nullptr;
+  bool owned = false;
+  if (dev_buf) {
+    if (buf_bytes < lay.total)
+      return fail(LBM_EINVAL, "lent buffer holds " + std::to_string(buf_bytes) + " bytes, " +
+                                  std::to_string(lay.total) + " needed");
+    if (reinterpret_cast<uintptr_t>(dev_buf) % kByteAlign != 0)
+      return fail(LBM_EINVAL, "lent buffer must be 256-byte aligned");
+    base = dev_buf;
+  } else {
+    if (hipMalloc(&base, lay.total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBM_ENOMEM, "hipMalloc of " + std::to_string(lay.total) + " bytes failed");
+    }
+    owned = true;
+  }
+  Slot &s = c->slots[id];
+  s = Slot();
+  s.used = true;
+  s.cs = *cs;
+  s.lat = lat;
+  s.lay = lay;
+  s.base = base;
+  s.owned = owned;
+  s.dev = make_dev(cs, lat, lay, base);
+  c->used += lay.total;
+  c->batch.dirty = true;
+  hipError_t e = lbm::launch_init(s.dev, cs->precision, cs->init, cs->T0, cs->gauss_amp,
+                                  cs->gauss_sigma, c->stream);
+  if (e == hipSuccess && cs->pattern == LBM_PATTERN_AB)
+    e = lbm::launch_fill_zero(s.dev.pop[1], lay.pop_bytes, c->stream);
+  if (e != hipSuccess) {
+    lbm_release(c, id);
+    return fail(LBM_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+  }
+  rc = restart_clock(c, s);
+  if (rc != LBM_OK) {
+    std::string msg = g_last_error;
+    lbm_release(c, id);
+    return fail(rc, msg);
+  }
+  *slot_out = id;
+  return LBM_OK;
+}
+
+int lbm_release(lbm_ctx *c, int slot) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(s);
+  if (s.series) (void)hipFree(s.series);
+  if (s.owned && s.base) (void)hipFree(s.base);
+  c->used -= s.lay.total;
+  s = Slot();
+  c->batch.dirty = true;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int slot, int64_t nsteps) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return LBM_OK;
+  if (slot == LBM_ALL) return step_all(c, nsteps);
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  return step_slot(c, c->slots[slot], nsteps);
+}
+
+int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  if (!out) return fail(LBM_EINVAL, "output is NULL");
+  Slot &s = c->slots[slot];
+  StatsDev d{};
+  rc = reduce_now(c, s, &d);
+  if (rc != LBM_OK) return rc;
+  fill_stats(s, d, s.step, s.dev.parity, out);
+  if (!out->finite) return fail(LBM_EUNSTABLE, "populations are not finite");
+  return LBM_OK;
+}
+
+int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  mask &= 63u;
+  int planes = 0;
+  for (int b = 0; b < 6; ++b) planes += (mask >> b) & 1u;
+  const size_t cells = (size_t)s.cs.nx * s.cs.ny;
+  if (!host || planes == 0 || n < planes * cells)
+    return fail(LBM_EINVAL, "host buffer too small or empty mask");
+  rc = ensure_scratch(c, planes * cells * sizeof(double));
+  if (rc != LBM_OK) return rc;
+  HIP_TRY(lbm::launch_fields(s.dev, s.cs.precision, mask, static_cast<double *>(c->scratch),
+                             c->stream));
+  HIP_TRY(hipMemcpyAsync(host, c->scratch, planes * cells * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_report(lbm_ctx *c, int slot, int64_t every, int32_t capacity) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  if (every < 0 || (every > 0 && capacity < 1)) return fail(LBM_EINVAL, "bad report schedule");
+  Slot &s = c->slots[slot];
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (s.series) (void)hipFree(s.series);
+  s.series = nullptr;
+  s.series_step.clear();
+  s.series_parity.clear();
+  s.report_every = every;
+  s.report_cap = every > 0 ? capacity : 0;
+  if (every > 0) {
+    if (hipMalloc(&s.series, (size_t)capacity * sizeof(StatsDev)) != hipSuccess) {
+      (void)hipGetLastError();
+      s.series = nullptr;
+      s.report_every = 0;
+      s.report_cap = 0;
+      return fail(LBM_ENOMEM, "cannot allocate the report ring");
+    }
+  }
+  c->batch.dirty = true;
+  return LBM_OK;
+}
+
+int lbm_series(lbm_ctx *c, int slot, lbm_stats *host, int32_t max, int32_t *count) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  if (!count || (max > 0 && !host)) return fail(LBM_EINVAL, "bad output");
+  Slot &s = c->slots[slot];
+  const int32_t k = std::min<int32_t>((int32_t)s.series_step.size(), std::max<int32_t>(max, 0));
+  *count = k;
+  if (k == 0) return LBM_OK;
+  std::vector<StatsDev> tmp(k);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(tmp.data(), s.series, k * sizeof(StatsDev), hipMemcpyDeviceToHost));
+  for (int32_t j = 0; j < k; ++j) fill_stats(s, tmp[j], s.series_step[j], s.series_parity[j], host + j);
+  return LBM_OK;
+}
+
+int lbm_state_load(lbm_ctx *c, int slot, const double *f, const double *g, size_t n) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  const size_t cnt = (size_t)lbm::kQ * s.cs.nx * s.cs.ny;
+  if (!f || !g || n < cnt) return fail(LBM_EINVAL, "population buffers too small");
+  rc = ensure_scratch(c, 2 * cnt * sizeof(double));
+  if (rc != LBM_OK) return rc;
+  double *df = static_cast<double *>(c->scratch);
+  double *dg = df + cnt;
+  HIP_TRY(hipMemcpyAsync(df, f, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(dg, g, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  s.dev.parity = 0;
+  HIP_TRY(lbm::launch_load(s.dev, s.cs.precision, df, dg, c->stream));
+  drop_graphs(s);
+  return restart_clock(c, s);
+}
+
+int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  const size_t cnt = (size_t)lbm::kQ * s.cs.nx * s.cs.ny;
+  if (!f || !g || n < cnt) return fail(LBM_EINVAL, "population buffers too small");
+  rc = ensure_scratch(c, 2 * cnt * sizeof(double));
+  if (rc != LBM_OK) return rc;
+  double *df = static_cast<double *>(c->scratch);
+  double *dg = df + cnt;
+  HIP_TRY(lbm::launch_save(s.dev, s.cs.precision, df, dg, c->stream));
+  HIP_TRY(hipMemcpyAsync(f, df, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(g, dg, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int xcd_remap) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
+  if (bx < 64 || bx % 64 != 0 || by < 1 || bx * by > 256 || (cpl != 1 && cpl != 2 && cpl != 4))
+    return fail(LBM_EINVAL, "tile: bx multiple of 64, bx*by <= 256, cpl in {1,2,4}");
+  LaunchCfg &L = c->launch[precision];
+  L.bx = bx;
+  L.by = by;
+  L.cpl = cpl;
+  L.xcd = xcd_remap ? 1 : 0;
+  for (auto &s : c->slots) drop_graphs(s);
+  return LBM_OK;
+}
+
+int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *xcd_remap) {
+  if (!c || !bx || !by || !cpl || !xcd_remap) return fail(LBM_EINVAL, "NULL argument");
+  if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
+  const LaunchCfg &L = c->launch[precision];
+  *bx = L.bx;
+  *by = L.by;
+  *cpl = L.cpl;
+  *xcd_remap = L.xcd;
+  return LBM_OK;
+}
+
+int lbm_set_graph_chunk(lbm_ctx *c, int chunk) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (chunk < 0 || chunk > 10000) return fail(LBM_EINVAL, "chunk out of range");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->graph_chunk = chunk;
+  for (auto &s : c->slots) drop_graphs(s);
+  drop_batch_graph(c);
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx *c) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_stream(lbm_ctx *c, void **stream) {
+  if (!c || !stream) return fail(LBM_EINVAL, "NULL argument");
+  *stream = c->stream;
+  return LBM_OK;
+}
+
+int lbm_slot_info(lbm_ctx *c, int slot, int64_t *step, int32_t *parity, size_t *bytes) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  const Slot &s = c->slots[slot];
+  if (step) *step = s.step;
+  if (parity) *parity = s.dev.parity;
+  if (bytes) *bytes = s.lay.total;
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner: times candidate tiles of the single-cavity step on a scratch
+// cavity and keeps the fastest per (precision, size class)
+
+namespace {
+
+std::string size_class(int precision, int nx, int ny) {
+  auto p2 = [](int v) { int p = 1; while (p < v) p <<= 1; return p; };
+  return std::string(precision == LBM_FP64 ? "fp64" : "fp32s") + "/" + std::to_string(p2(nx)) +
+         "x" + std::to_string(p2(ny));
+}
+
+// The cache is a flat JSON object {"<class>": [bx, by, cpl, xcd, us_per_step], ...}.
+std::map<std::string, std::vector<double>> read_cache(const char *path) {
+  std::map<std::string, std::vector<double>> m;
+  if (!path) return m;
+  std::ifstream in(path);
+  if (!in) return m;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string s = ss.str();
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t end = s.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = s.substr(pos + 1, end - pos - 1);
+    const size_t lb = s.find('[', end), rb = s.find(']', end);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+    std::vector<double> v;
+    std::stringstream nums(s.substr(lb + 1, rb - lb - 1));
+    std::string tok;
+    while (std::getline(nums, tok, ',')) v.push_back(std::atof(tok.c_str()));
+    if (v.size() >= 4) m[key] = v;
+    pos = rb + 1;
+  }
+  return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, std::vector<double>> &m) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  std::ofstream out(tmp);
+  if (!out) return;
+  out << "{\n";
+  size_t k = 0;
+  for (const auto &kv : m) {
+    out << "  \"" << kv.first << "\": [";
+    for (size_t j = 0; j < kv.second.size(); ++j) out << (j ? ", " : "") << kv.second[j];
+    out << "]" << (++k < m.size() ? "," : "") << "\n";
+  }
+  out << "}\n";
+  out.close();
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
+  const std::string key = size_class(precision, nx, ny);
+  auto cache = read_cache(cache_path);
+  auto it = cache.find(key);
+  if (it != cache.end())
+    return lbm_set_launch(c, precision, (int)it->second[0], (int)it->second[1],
+                          (int)it->second[2], (int)it->second[3]);
+  lbm_case cs{};
+  cs.nx = nx;
+  cs.ny = ny;
+  cs.precision = precision;
+  cs.pattern = LBM_PATTERN_AA;
+  cs.param_mode = LBM_PARAM_DIMENSIONLESS;
+  cs.init = LBM_INIT_SOLID_AT_TM;
+  cs.Ra = 1e6; cs.Pr = 1.0; cs.Ste = 1.0; cs.Ma = 0.1;
+  cs.Cp = 1.0; cs.Th = 1.0; cs.Tm = 0.0; cs.rho0 = 1.0;
+  cs.heater_center = 0.5; cs.heater_width = 0.25;
+  cs.k0_g = cs.k2_g = cs.k0_f = cs.k1_f = std::nan("");
+  cs.gauss_sigma = 1.0;
+  lbm_lattice lat;
+  std::string why;
+  if (derive(&cs, &lat, why) != LBM_OK) return fail(LBM_EINVAL, why);
+  const Layout lay = layout_of(&cs, lat);
+  void *base = nullptr;
+  if (hipMalloc(&base, lay.total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, "autotune scratch cavity does not fit");
+  }
+  CavDev d = make_dev(&cs, lat, lay, base);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  LaunchCfg best;
+  float best_ms = 1e30f;
+  const LaunchCfg saved = c->launch[precision];
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      lbm::launch_init(d, precision, LBM_INIT_SOLID_AT_TM, 0, 0, 1, c->stream) != hipSuccess ||
+      lbm::launch_fill_zero(d.cumq, lay.cumq_bytes, c->stream) != hipSuccess) {
+    rc = fail(LBM_EDEVICE, "autotune set-up failed");
+  }
+  const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
+  const int cpls[] = {1, 2, 4};
+  const int reps = 10;
+  for (const auto &sh : shapes) {
+    for (int cpl : cpls) {
+      for (int xcd = 0; xcd < 2 && rc == LBM_OK; ++xcd) {
+        LaunchCfg cfg;
+        cfg.bx = sh[0];
+        cfg.by = sh[1];
+        cfg.cpl = cpl;
+        cfg.xcd = xcd;
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+          e = lbm::launch_step(d, precision, cfg, c->stream);
+          d.parity ^= 1;
+        }
+        e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
+        for (int k = 0; k < reps && e == hipSuccess; ++k) {
+          e = lbm::launch_step(d, precision, cfg, c->stream);
+          d.parity ^= 1;
+        }
+        e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
+        e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+        float ms = 0.0f;
+        e = e == hipSuccess ? hipEventElapsedTime(&ms, e0, e1) : e;
+        if (e != hipSuccess) {
+          rc = fail(LBM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cfg;
+        }
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(base);
+  if (rc != LBM_OK) {
+    c->launch[precision] = saved;
+    return rc;
+  }
+  cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best.xcd,
+                1000.0 * best_ms / reps};
+  write_cache(cache_path, cache);
+  return lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best.xcd);
+}

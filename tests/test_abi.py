@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, and its host-only calls (validation, parameter derivation,
+footprint) behave as documented.  No kernel runs here."""
+import math
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_1909_13086_amd as P
+from btrirt_workloads import batch_sweep, cavity, large_cavity, small_cavity
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(lbm_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    names = declared_functions()
+    assert "lbm_step" in names and "lbm_set_case" in names
+    for n in sorted(names):
+        assert hasattr(lib, n), f"{n} declared but not exported"
+    assert set(P.EXPORTS) <= names
+
+
+def test_version_and_errors():
+    assert "gfx950" in P.lbm_version()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert P.lbm_strerror(code)
+    assert P.lbm_strerror(-99) == "unknown error"
+
+
+@pytest.mark.parametrize("case", [small_cavity("literal"), small_cavity("eq6"), small_cavity("distinct"),
+                                  large_cavity(), *batch_sweep()[:6],
+                                  cavity(17, 9, heater_center=0.1, heater_width=0.5, Pr=6.2, Ste=0.125, Ra=1e8)])
+def test_derivation_matches_oracle(case):
+    """The library and the oracle derive the lattice parameters independently."""
+    got = P.lbm_derive(P.make_case(case))
+    want = oracle.derive(oracle.case_from_dict(case))
+    for k in ("nu", "alpha", "gbeta", "latent", "k0_g", "k1_g", "k2_g", "k0_f", "k1_f", "k2_f"):
+        assert getattr(got, k) == pytest.approx(getattr(want, k), rel=1e-15, abs=0), k
+    if want.n_heater > 0:
+        assert (got.heater_lo, got.heater_hi) == (want.heater_lo, want.heater_hi)
+    assert got.n_heater == want.n_heater
+    assert got.pitch % 64 == 0 and got.pitch >= case["nx"]
+
+
+def test_literal_small_cavity_rates():
+    lat = P.lbm_derive(P.make_case(small_cavity("literal")))
+    assert lat.k0_g == 1.0 and lat.k2_g == 1.0
+    assert lat.k1_g == pytest.approx(1.637060, abs=1e-6)
+    assert (lat.heater_lo, lat.heater_hi, lat.n_heater) == (48, 79, 32)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-3), dict(precision=2), dict(pattern=5), dict(init=7), dict(param_mode=3),
+    dict(Ra=0.0), dict(Th=0.0), dict(k0_g=2.0), dict(k2_g=0.0), dict(k1_f=-1.0), dict(Cp=0.0),
+    dict(heater_center=math.inf), dict(init=2, gauss_sigma=0.0),
+    dict(param_mode=1, nu=0.1, alpha=0.0, latent=1.0), dict(param_mode=1, nu=0.1, alpha=0.1, latent=-1.0),
+])
+def test_invalid_cases_rejected(bad):
+    c = P.make_case(cavity(32, 16), **bad)
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_derive(c)
+    assert ei.value.code == P.LBM_EINVAL
+    assert P.lbm_footprint(c) == 0
+
+
+def test_footprint_layout():
+    for prec, elem in ((P.LBM_FP64, 8), (P.LBM_FP32_SHIFTED, 4)):
+        for pat, lattices in ((P.LBM_PATTERN_AA, 1), (P.LBM_PATTERN_AB, 2)):
+            c = P.make_case(large_cavity(), precision=prec, pattern=pat)
+            pops = 18 * 2048 * 1024 * elem
+            assert P.lbm_footprint(c) == lattices * pops + 2048 * 8
+    # ragged width: rows padded to a 64-cell pitch
+    c = P.make_case(cavity(100, 10))
+    assert P.lbm_footprint(c) == (18 * 128 * 10 * 8 + 255) // 256 * 256 + 1024
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible")
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_create(0, None, 0, 1)
+    assert ei.value.code == P.LBM_EDEVICE

@@ -1,0 +1,90 @@
+"""Batched launch: many cavities of uneven size and precision advance in one
+launch per step (optionally replayed from a captured graph); each cavity's
+result must equal its own solo run bitwise."""
+import numpy as np
+import pytest
+
+from btrirt_workloads import batch_sweep, cavity
+from tests.test_gpu_parity import _random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1909_13086_amd as P
+    return P
+
+
+def _cases(P):
+    return [
+        dict(cavity(256, 128, Ra=1e6, heater_center=0.3), precision=P.LBM_FP32_SHIFTED),
+        dict(cavity(130, 33, periodic_x=1, Ra=3e5, heater_center=0.7), precision=P.LBM_FP64),
+        dict(cavity(64, 64, Ra=1e7), precision=P.LBM_FP64, pattern=P.LBM_PATTERN_AB),
+        dict(cavity(77, 21, Ra=2e6, heater_center=0.5), precision=P.LBM_FP32_SHIFTED,
+             pattern=P.LBM_PATTERN_AB),
+        dict(cavity(320, 160, Ra=1e8, heater_center=0.2), precision=P.LBM_FP32_SHIFTED),
+    ]
+
+
+def _solo(P, case, f0, g0, steps):
+    with P.Context(device=0, max_slots=1) as ctx:
+        s = ctx.add(case)
+        ctx.state_load(s, f0, g0)
+        ctx.step(s, steps)
+        return ctx.state_save(s)
+
+
+@pytest.mark.parametrize("chunk", [0, 10])
+@pytest.mark.parametrize("steps", [1, 33])
+def test_batch_equals_solo_bitwise(P, chunk, steps):
+    print(f"case batch of 5, graph chunk {chunk}, steps {steps}", flush=True)
+    cases = _cases(P)
+    states = [_random_state(40 + k, c["nx"], c["ny"]) for k, c in enumerate(cases)]
+    with P.Context(device=0, max_slots=8) as ctx:
+        ctx.set_graph_chunk(chunk)
+        slots = []
+        for c, (f0, g0) in zip(cases, states):
+            s = ctx.add(c)
+            ctx.state_load(s, f0, g0)
+            slots.append(s)
+        # one slot starts one step ahead, so parities differ inside the batch
+        ctx.step(slots[1], 1)
+        ctx.step(P.LBM_ALL, steps)
+        got = [ctx.state_save(s) for s in slots]
+        infos = [ctx.info(s) for s in slots]
+    for k, (c, (f0, g0)) in enumerate(zip(cases, states)):
+        n = steps + (1 if k == 1 else 0)
+        assert infos[k][0] == n
+        want = _solo(P, c, f0, g0, n)
+        assert np.array_equal(got[k][0], want[0]) and np.array_equal(got[k][1], want[1]), k
+
+
+def test_batch_membership_changes_keep_results(P):
+    """Slots join and leave between batched chunks; the captured graph is reused."""
+    cases = _cases(P)
+    states = [_random_state(60 + k, c["nx"], c["ny"]) for k, c in enumerate(cases)]
+    with P.Context(device=0, max_slots=8) as ctx:
+        ctx.set_graph_chunk(10)
+        sl = {}
+        for k in (0, 1, 2):
+            sl[k] = ctx.add(cases[k])
+            ctx.state_load(sl[k], *states[k])
+        ctx.step(P.LBM_ALL, 20)
+        ctx.release(sl.pop(1))
+        for k in (3, 4):
+            sl[k] = ctx.add(cases[k])
+            ctx.state_load(sl[k], *states[k])
+        ctx.step(P.LBM_ALL, 20)
+        got = {k: ctx.state_save(s) for k, s in sl.items()}
+        steps = {k: ctx.info(s)[0] for k, s in sl.items()}
+    assert steps == {0: 40, 2: 40, 3: 20, 4: 20}
+    for k, st in got.items():
+        want = _solo(P, cases[k], *states[k], steps[k])
+        assert np.array_equal(st[0], want[0]) and np.array_equal(st[1], want[1]), k
+
+
+def test_batch_sweep_generator_shapes():
+    cav = batch_sweep()
+    assert len(cav) == 64
+    assert all(256 <= c["nx"] <= 1024 and c["nx"] % 64 == 0 and c["ny"] == c["nx"] // 2 for c in cav)

@@ -1,0 +1,62 @@
+"""FP32 shifted-population path: populations stored as f_i - w_i rho0 and
+g_i - w_i Cp Tm in FP32, diagnostics reduced in FP64.  Error against the FP64
+oracle is reported per result (liquid-fraction field, melt fraction, Nusselt
+number); the bar is 1e-4 in melt fraction and 0.5 % in Nusselt number."""
+import numpy as np
+import pytest
+
+import oracle
+from btrirt_workloads import small_cavity
+from tests.test_gpu_parity import _random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1909_13086_amd as P
+    return P
+
+
+@pytest.mark.parametrize("variant", ["literal", "eq6"])
+def test_fp32_shifted_small_cavity_to_20k_steps(P, variant):
+    case = dict(small_cavity(variant), precision=P.LBM_FP32_SHIFTED)
+    print(f"case small_cavity[{variant}] FP32 shifted to 20000 steps", flush=True)
+    o = oracle.Oracle(oracle.case_from_dict(case)).init_solid()
+    rows = []
+    with P.Context(device=0, max_slots=2) as ctx:
+        s = ctx.add(case)
+        done = 0
+        for t in (5000, 10000, 20000):
+            ctx.step(s, t - done)
+            o.step(t - done)
+            done = t
+            st, ost = ctx.reduce(s), o.stats()
+            fl_err = float(np.max(np.abs(ctx.fields(s, 2)["fl"] - o.fields()["fl"])))
+            dphi = abs(st["melt_fraction"] - ost["melt_fraction"])
+            dnu = abs(st["nusselt"] - ost["nusselt"]) / abs(ost["nusselt"])
+            rows.append((t, fl_err, dphi, dnu))
+            print(f"  t={t}: Linf(fl)={fl_err:.2e} |dphi|={dphi:.2e} |dNu|/Nu={dnu:.2e} "
+                  f"phi={ost['melt_fraction']:.5f} Nu={ost['nusselt']:.4f} "
+                  f"budget={st['budget_residual']:.2e}", flush=True)
+            assert dphi <= 1e-4
+            assert dnu <= 5e-3
+            assert st["finite"] == 1
+
+
+def test_fp32_shifted_short_run_tracks_oracle(P):
+    from btrirt_workloads import cavity
+    nx, ny = 96, 40
+    case = dict(cavity(nx, ny, param_mode=1, nu=0.04, alpha=0.06, gbeta=3e-3, latent=0.8, Tm=0.1,
+                       Th=0.9, heater_center=0.3, heater_width=0.4), precision=P.LBM_FP32_SHIFTED)
+    f0, g0 = _random_state(77, nx, ny)
+    with P.Context(device=0, max_slots=1) as ctx:
+        s = ctx.add(case)
+        ctx.state_load(s, f0, g0)
+        ctx.step(s, 25)
+        fg, gg = ctx.state_save(s)
+    o = oracle.Oracle(oracle.case_from_dict(case)).set_populations(f0, g0).step(25)
+    fo, go = o.populations()
+    # FP32 storage: a few units in the last place of values of order 1
+    assert np.max(np.abs(fg - fo)) <= 2e-6
+    assert np.max(np.abs(gg - go)) <= 2e-6

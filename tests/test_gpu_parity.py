@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+FP64 bar (from the problem statement of this path): max|dH|, max|du| <= 1e-10
+after 2000 steps.  Storage patterns and tile shapes must agree bitwise, since
+they only change where the same arithmetic reads and writes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from btrirt_workloads import cavity, large_cavity, random_planes, small_cavity
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1909_13086_amd as P
+    return P
+
+
+@pytest.fixture()
+def ctx(P):
+    c = P.Context(device=0, max_slots=16)
+    yield c
+    c.close()
+
+
+def oracle_run(case, steps, f0=None, g0=None):
+    o = oracle.Oracle(oracle.case_from_dict(case))
+    if f0 is not None:
+        o.set_populations(f0, g0)
+    else:
+        o.init_solid()
+    o.step(steps)
+    return o
+
+
+def max_field_err(got, want, names=("H", "T", "fl", "ux", "uy", "rho")):
+    return {n: float(np.max(np.abs(got[n] - want[n]))) for n in names}
+
+
+@pytest.mark.parametrize("variant", ["literal", "eq6", "distinct"])
+def test_small_cavity_2000_steps(ctx, variant):
+    case = small_cavity(variant)
+    print(f"case small_cavity[{variant}] 128x64 FP64 2000 steps", flush=True)
+    s = ctx.add(case)
+    ctx.step(s, 2000)
+    got, st = ctx.fields(s), ctx.reduce(s)
+    o = oracle_run(case, 2000)
+    want, ost = o.fields(), o.stats()
+    err = max_field_err(got, want)
+    assert err["H"] <= TOL and err["ux"] <= TOL and err["uy"] <= TOL, err
+    assert max(err.values()) <= TOL, err
+    assert st["step"] == 2000 and st["finite"] == 1
+    assert st["melt_fraction"] == pytest.approx(ost["melt_fraction"], abs=1e-12)
+    assert st["nusselt"] == pytest.approx(ost["nusselt"], rel=1e-10)
+    assert st["heater_q"] == pytest.approx(ost["heater_q"], rel=1e-10)
+    assert st["total_H"] == pytest.approx(ost["total_H"], rel=1e-12)
+    assert st["heat_in_cum"] == pytest.approx(ost["heat_in_cum"], rel=1e-12)
+    assert st["mass"] == pytest.approx(ost["mass"], rel=1e-13)
+    assert st["max_u"] == pytest.approx(ost["max_u"], rel=1e-8)
+    assert abs(st["budget_residual"]) <= 1e-12 * st["total_H"]
+    assert st["fourier"] == pytest.approx(ost["fourier"], rel=1e-14)
+
+
+def _random_state(seed, nx, ny):
+    r = random_planes(seed, 18, ny, nx)
+    f = W[:, None, None] * (1.0 + 0.1 * (r[:9] - 0.5))
+    g = W[:, None, None] * (2.5 * r[9:] - 0.5)  # enthalpy spans solid, mushy and liquid cells
+    return f, g
+
+
+GEOMS = [
+    # nx, ny, periodic_x, periodic_y, heater centre, width
+    (1, 40, 1, 0, 0.5, 1.0),
+    (3, 5, 0, 0, 0.5, 1.0),
+    (65, 7, 0, 0, 0.1, 0.5),
+    (130, 33, 1, 0, 0.9, 0.4),
+    (64, 64, 1, 1, 0.5, 0.25),
+    (200, 3, 0, 1, 0.5, 0.25),
+    (77, 1, 0, 0, 0.5, 0.3),
+]
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=[f"{g[0]}x{g[1]}p{g[2]}{g[3]}" for g in GEOMS])
+@pytest.mark.parametrize("steps", [1, 8, 13])
+def test_random_states_and_boundaries(ctx, P, geom, steps):
+    nx, ny, px, py, hc, hw = geom
+    case = cavity(nx, ny, periodic_x=px, periodic_y=py, heater_center=hc, heater_width=hw,
+                  param_mode=1, nu=0.04, alpha=0.06, gbeta=3e-3, latent=0.8, Tm=0.1, Th=0.9,
+                  k0_g=0.9, k2_g=1.2, k0_f=1.1, k1_f=0.85)
+    print(f"case random {nx}x{ny} periodic=({px},{py}) heater=({hc},{hw}) steps={steps}", flush=True)
+    f0, g0 = _random_state(1000 + nx + ny, nx, ny)
+    s = ctx.add(case)
+    ctx.state_load(s, f0, g0)
+    ctx.step(s, steps)
+    fg, gg = ctx.state_save(s)
+    o = oracle_run(case, steps, f0, g0)
+    fo, go = o.populations()
+    assert np.max(np.abs(fg - fo)) <= 1e-13
+    assert np.max(np.abs(gg - go)) <= 1e-13
+    err = max_field_err(ctx.fields(s), o.fields())
+    assert max(err.values()) <= 1e-13, err
+    st, ost = ctx.reduce(s), o.stats()
+    for k in ("melt_fraction", "total_H", "mass", "heater_q", "heat_in_cum"):
+        assert st[k] == pytest.approx(ost[k], rel=1e-12, abs=1e-13), k
+
+
+def test_state_load_save_round_trip(ctx):
+    nx, ny = 70, 9
+    f0, g0 = _random_state(5, nx, ny)
+    s = ctx.add(cavity(nx, ny))
+    ctx.state_load(s, f0, g0)
+    f1, g1 = ctx.state_save(s)
+    assert np.max(np.abs(f1 - f0)) <= 2e-16 and np.max(np.abs(g1 - g0)) <= 4e-16
+
+
+def _run_state(ctx, P, case, steps, f0, g0, launch=None):
+    if launch is not None:
+        ctx.set_launch(case.get("precision", 0), *launch)
+    s = ctx.add(case)
+    ctx.state_load(s, f0, g0)
+    ctx.step(s, steps)
+    out = ctx.state_save(s)
+    ctx.release(s)
+    return out
+
+
+@pytest.mark.parametrize("steps", [37, 38])
+def test_patterns_and_tiles_agree_bitwise(ctx, P, steps):
+    base = small_cavity("distinct")
+    f0, g0 = _random_state(9, 128, 64)
+    ref = _run_state(ctx, P, dict(base, pattern=P.LBM_PATTERN_AB), steps, f0, g0)
+    for launch in [(256, 1, 1, 1), (64, 4, 2, 0), (128, 2, 4, 1), (64, 1, 1, 0)]:
+        got = _run_state(ctx, P, dict(base), steps, f0, g0, launch)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), launch
+    ctx.set_launch(0, 256, 1, 1, 1)
+
+
+def test_graph_chunks_equal_plain_launches(ctx, P):
+    case = small_cavity("eq6")
+    f0, g0 = _random_state(3, 128, 64)
+    ref = _run_state(ctx, P, case, 47, f0, g0)
+    ctx.set_graph_chunk(10)
+    got = _run_state(ctx, P, case, 47, f0, g0)
+    ctx.set_graph_chunk(0)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_recorded_series_matches_direct_reductions(ctx):
+    case = small_cavity("eq6")
+    s = ctx.add(case)
+    ctx.set_report(s, 100, 16)
+    ctx.step(s, 450)
+    series = ctx.series(s)
+    assert [e["step"] for e in series] == [100, 200, 300, 400]
+    s2 = ctx.add(case)
+    for e in series:
+        ctx.step(s2, e["step"] - ctx.info(s2)[0])
+        d = ctx.reduce(s2)
+        for k in ("melt_fraction", "total_H", "heat_in_cum", "nusselt", "budget_residual"):
+            assert e[k] == d[k], k
+
+
+def test_large_cavity_full_size_20_steps(ctx):
+    case = large_cavity()
+    print("case 2048x1024 FP64 20 steps vs oracle", flush=True)
+    f0, g0 = _random_state(21, 2048, 1024)
+    s = ctx.add(case)
+    ctx.state_load(s, f0, g0)
+    ctx.step(s, 20)
+    got = ctx.fields(s)
+    o = oracle_run(case, 20, f0, g0)
+    err = max_field_err(got, o.fields())
+    assert max(err.values()) <= 1e-12, err
+    st, ost = ctx.reduce(s), o.stats()
+    assert st["total_H"] == pytest.approx(ost["total_H"], rel=1e-13)
+    assert st["melt_fraction"] == pytest.approx(ost["melt_fraction"], abs=1e-13)
+
+
+def test_non_finite_state_is_reported(ctx, P):
+    nx, ny = 16, 8
+    f0, g0 = _random_state(2, nx, ny)
+    g0[0, 3, 5] = np.nan
+    s = ctx.add(cavity(nx, ny))
+    ctx.state_load(s, f0, g0)
+    with pytest.raises(P.LbmError) as ei:
+        ctx.reduce(s)
+    assert ei.value.code == P.LBM_EUNSTABLE
+    assert ctx.reduce(s, allow_unstable=True)["finite"] == 0
+
+
+def test_budget_admission(P):
+    case = P.make_case(cavity(256, 128))
+    need = P.lbm_footprint(case)
+    with P.Context(device=0, hbm_budget=2 * need + need // 2, max_slots=4, lend_memory=False) as c:
+        a = c.add(case)
+        c.add(case)
+        with pytest.raises(P.LbmError) as ei:
+            c.add(case)
+        assert ei.value.code == P.LBM_ENOMEM
+        c.release(a)
+        c.add(case)
