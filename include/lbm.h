@@ -126,8 +126,9 @@ const char *lbm_last_error(void);
  * diffusivity, non-positive Ra/Pr/Ste/Ma or Th <= Tm in dimensionless mode,
  * unknown enums, sizes < 1). */
 int lbm_derive(const lbm_case *cs, lbm_lattice *out);
-/* Device bytes one slot of this case occupies (populations, strip-flux
- * accumulators, reduction scratch); 0 for an invalid case. */
+/* Device bytes one slot of this case occupies (population planes, per-column
+ * strip-flux accumulators, diagnostics at load); 0 for an invalid case.
+ * A lent buffer must be at least this large and 256-byte aligned. */
 size_t lbm_footprint(const lbm_case *cs);
 /* Library version string. */
 const char *lbm_version(void);
@@ -144,7 +145,8 @@ void lbm_destroy(lbm_ctx *c);
 /* Admits a cavity: validates the case, reserves its footprint against the
  * budget (LBM_ENOMEM without side effects when it does not fit), binds
  * memory (dev_buf of buf_bytes >= lbm_footprint, or NULL to let the library
- * allocate) and writes the initial state of cs->init at step 0.  Blocks. */
+ * allocate) and enqueues the initial state of cs->init at step 0.  With a
+ * lent buffer nothing waits for the device; library allocation may. */
 int lbm_set_case(lbm_ctx *c, const lbm_case *cs, void *dev_buf, size_t buf_bytes, int *slot_out);
 /* Returns a slot's footprint to the budget and frees library-owned memory. */
 int lbm_release(lbm_ctx *c, int slot);
@@ -155,6 +157,16 @@ int lbm_release(lbm_ctx *c, int slot);
  * slot, or for every resident slot with slot = LBM_ALL (one batched launch
  * per step covers all cavities).  Asynchronous. */
 int lbm_step(lbm_ctx *c, int slot, int64_t nsteps);
+/* Advances slots[j] by nsteps[j] steps (each >= 0) in batched launches: one
+ * launch per step covers every listed cavity still short of its count, so
+ * requests of different lengths share the device (continuous batching).
+ * Asynchronous.  Each result equals that of lbm_step on the slot alone. */
+int lbm_step_many(lbm_ctx *c, int count, const int32_t *slots, const int64_t *nsteps);
+/* Capacity of one cache group of the batched launch (default 160 MiB): within
+ * a chunk of graph-replayed steps, each group of cavities whose footprints
+ * sum to at most this advances through all its steps before the next group,
+ * so its populations stay in the last-level cache. */
+int lbm_set_group_bytes(lbm_ctx *c, size_t bytes);
 /* Diagnostics of the current state.  Blocks.  Returns LBM_EUNSTABLE (with
  * *out filled) when a population is not finite. */
 int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out);

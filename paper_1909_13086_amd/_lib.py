@@ -29,7 +29,9 @@ EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_set_case", "lbm_release", "lbm_step", "lbm_reduce",
     "lbm_fields", "lbm_set_report", "lbm_series", "lbm_state_load", "lbm_state_save",
     "lbm_set_launch", "lbm_get_launch", "lbm_set_graph_chunk", "lbm_autotune", "lbm_sync",
-    "lbm_stream", "lbm_slot_info",
+    "lbm_stream", "lbm_slot_info", "lbm_step_many", "lbm_set_group_bytes",
+    "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
+    "lbm_server_request", "lbm_server_summary",
 )
 
 
@@ -124,6 +126,9 @@ def lib():
                                              ctypes.POINTER(ctypes.c_int)]),
             "lbm_release": (ctypes.c_int, [vp, ctypes.c_int]),
             "lbm_step": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64]),
+            "lbm_step_many": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+            "lbm_set_group_bytes": (ctypes.c_int, [vp, ctypes.c_size_t]),
             "lbm_reduce": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_stats)]),
             "lbm_fields": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_uint32, _dp, ctypes.c_size_t]),
             "lbm_set_report": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int32]),
@@ -208,6 +213,17 @@ def lbm_release(ctx, slot):
 
 def lbm_step(ctx, slot, nsteps):
     _check(lib().lbm_step(ctx, int(slot), int(nsteps)))
+
+
+def lbm_step_many(ctx, slots, nsteps):
+    n = len(slots)
+    a = (ctypes.c_int32 * max(n, 1))(*[int(v) for v in slots])
+    b = (ctypes.c_int64 * max(n, 1))(*[int(v) for v in nsteps])
+    _check(lib().lbm_step_many(ctx, n, a, b))
+
+
+def lbm_set_group_bytes(ctx, nbytes):
+    _check(lib().lbm_set_group_bytes(ctx, int(nbytes)))
 
 
 def lbm_reduce(ctx, slot, allow_unstable=False):

@@ -66,6 +66,12 @@ class Context:
     def step(self, slot, n):
         L.lbm_step(self.h, slot, n)
 
+    def step_many(self, slots, nsteps):
+        L.lbm_step_many(self.h, slots, nsteps)
+
+    def set_group_bytes(self, nbytes):
+        L.lbm_set_group_bytes(self.h, nbytes)
+
     def reduce(self, slot, allow_unstable=False):
         return L.lbm_reduce(self.h, slot, allow_unstable)
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace lbm {
 
@@ -79,5 +80,8 @@ hipError_t launch_load(const CavDev &c, int precision, const double *f, const do
 hipError_t launch_save(const CavDev &c, int precision, double *f, double *g, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy_stats(const StatsDev *src, StatsDev *dst, hipStream_t s);
+
+// Records the message returned by lbm_last_error() on this thread.
+void set_last_error(const std::string &msg);
 
 }  // namespace lbm

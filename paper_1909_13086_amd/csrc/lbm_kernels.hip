@@ -344,18 +344,25 @@ __global__ __launch_bounds__(256) void k_step(CavDev c, int tiles_x, int xcd) {
   }
 }
 
-// Batched step: a grid-stride loop over tiles of many cavities.  hdr holds
-// {first tile, tile count} of this precision, read on the device so that a
-// captured launch stays valid when cavities join or leave.  Cavity j
-// advances in this launch only while launch_index < active_steps(j); its
-// storage parity is its chunk-start parity flipped by the launch index.
+// Batched step over tiles of many cavities.  hdr holds {first tile, tile
+// count} of this launch, read on the device so that a captured launch stays
+// valid when cavities join or leave.  The tile list is cut into 8 contiguous
+// bands, one per XCD (workgroups are dispatched round-robin over the XCDs),
+// and each XCD's workgroups stride through its band, so neighbouring tiles
+// share that XCD's L2.  Cavity j advances in this launch only while
+// launch_index < active_steps(j); its storage parity is its chunk-start
+// parity flipped by the launch index.
 template <typename S, typename R>
 __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ cavs,
                                                     const BatchTile *__restrict__ tiles,
                                                     const int32_t *__restrict__ hdr,
                                                     int tile_rows, int launch_index) {
   const int first = hdr[0], ntiles = hdr[1];
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
+  const int nbx = (gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int t0 = (int)((int64_t)ntiles * xcd / kXcds);
+  const int t1 = (int)((int64_t)ntiles * (xcd + 1) / kXcds);
+  for (int t = t0 + lb; t < t1; t += nbx) {
     const BatchTile tile = tiles[first + t];
     CavDev c = cavs[tile.cav];
     if (launch_index >= c.active_steps) continue;

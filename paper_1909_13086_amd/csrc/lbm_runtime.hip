@@ -142,6 +142,7 @@ int derive(const lbm_case *cs, lbm_lattice *out, std::string &why) {
 struct Layout {
   size_t pop_bytes;   // one lattice (18 planes)
   size_t cumq_off, cumq_bytes;
+  size_t aux_off;     // diagnostics of the state at load (reference enthalpy)
   size_t total;
 };
 
@@ -152,7 +153,8 @@ Layout layout_of(const lbm_case *cs, const lbm_lattice &lat) {
   const size_t lattices = cs->pattern == LBM_PATTERN_AB ? 2 : 1;
   L.cumq_off = lattices * L.pop_bytes;
   L.cumq_bytes = round_up((size_t)cs->nx * sizeof(double), kByteAlign);
-  L.total = L.cumq_off + L.cumq_bytes;
+  L.aux_off = L.cumq_off + L.cumq_bytes;
+  L.total = L.aux_off + round_up(sizeof(StatsDev), kByteAlign);
   return L;
 }
 
@@ -165,7 +167,7 @@ struct Slot {
   void *base = nullptr;
   bool owned = false;
   int64_t step = 0;
-  double E0 = 0.0;
+  StatsDev *e0_dev = nullptr;  // diagnostics of the state at load, on the device
   // diagnostics recorded during lbm_step
   int64_t report_every = 0;
   int32_t report_cap = 0;
@@ -177,23 +179,30 @@ struct Slot {
   int graph_chunk = 0;
 };
 
+// Batched execution.  Resident cavities are packed into cache groups whose
+// summed footprint fits the last-level (Infinity) cache; within a chunk every
+// group advances all its steps before the next group starts, so after its
+// first step a group's populations are served from that cache.  Groups are
+// independent cavities, so the order changes no result.
 struct Batch {
   CavDev *cavs_dev = nullptr;
   BatchTile *tiles_dev = nullptr;
-  int32_t *hdr_dev = nullptr;     // {first, count} for FP64 then FP32
-  size_t cav_cap = 0, tile_cap = 0;
+  int32_t *hdr_dev = nullptr;     // per (group, precision): {first tile, tile count}
+  size_t cav_cap = 0, tile_cap = 0, hdr_cap = 0;
   CavDev *cavs_host = nullptr;    // pinned staging
   BatchTile *tiles_host = nullptr;
   int32_t *hdr_host = nullptr;
-  int ntiles[2] = {0, 0};         // per precision
   std::vector<int> members;       // slot ids in cavity-array order
+  std::vector<int> group_precs;   // per group: bit p set when it holds precision p
   bool dirty = true;
-  hipGraphExec_t graph = nullptr; // valid while the device buffers stay put
+  hipGraphExec_t graph = nullptr; // valid while the device buffers and the group shape stay
   int graph_chunk = 0;
-  int graph_precs = 0;            // bit p set: precision p launched in the graph
+  std::vector<int> graph_shape;   // group_precs the graph was captured for
 };
 
 }  // namespace
+
+void lbm::set_last_error(const std::string &msg) { g_last_error = msg; }
 
 struct lbm_ctx {
   int device = 0;
@@ -203,12 +212,13 @@ struct lbm_ctx {
   std::vector<Slot> slots;
   double *partials = nullptr;
   StatsDev *stats_dev = nullptr;
-  StatsDev *stats_host = nullptr;  // pinned
+  StatsDev *stats_host = nullptr;  // pinned, 2 entries: current state and state at load
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
   LaunchCfg launch[2];
   int graph_chunk = 0;
   int num_cus = 256;
+  size_t group_bytes = size_t(160) << 20;  // cache-group capacity of the batched launch
   Batch batch;
 };
 
@@ -289,16 +299,21 @@ CavDev make_dev(const lbm_case *cs, const lbm_lattice &lat, const Layout &lay, v
   return d;
 }
 
-int reduce_now(lbm_ctx *c, Slot &s, StatsDev *out_host) {
+// Diagnostics of the current state; *e0 gets the total enthalpy at load.
+int reduce_now(lbm_ctx *c, Slot &s, StatsDev *out_host, double *e0) {
   HIP_TRY(lbm::launch_reduce(s.dev, s.cs.precision, c->partials, c->stats_dev, c->stream));
   HIP_TRY(hipMemcpyAsync(c->stats_host, c->stats_dev, sizeof(StatsDev), hipMemcpyDeviceToHost,
                          c->stream));
+  HIP_TRY(hipMemcpyAsync(c->stats_host + 1, s.e0_dev, sizeof(StatsDev), hipMemcpyDeviceToHost,
+                         c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  *out_host = *c->stats_host;
+  *out_host = c->stats_host[0];
+  *e0 = c->stats_host[1].total_H;
   return LBM_OK;
 }
 
-void fill_stats(const Slot &s, const StatsDev &d, int64_t step, int32_t parity, lbm_stats *o) {
+void fill_stats(const Slot &s, const StatsDev &d, double E0, int64_t step, int32_t parity,
+                lbm_stats *o) {
   std::memset(o, 0, sizeof(*o));
   o->step = step;
   o->melt_fraction = d.melt_fraction;
@@ -309,7 +324,7 @@ void fill_stats(const Slot &s, const StatsDev &d, int64_t step, int32_t parity, 
                    : 0.0;
   o->total_H = d.total_H;
   o->heat_in_cum = d.heat_in_cum;
-  o->budget_residual = d.total_H - s.E0 - d.heat_in_cum;
+  o->budget_residual = d.total_H - E0 - d.heat_in_cum;
   o->mass = d.mass;
   o->max_u = d.max_u;
   o->fourier = s.lat.alpha * (double)step / ((double)s.cs.ny * (double)s.cs.ny);
@@ -317,16 +332,15 @@ void fill_stats(const Slot &s, const StatsDev &d, int64_t step, int32_t parity, 
   o->parity = parity;
 }
 
-// Resets step, strip budget and reference enthalpy after a new state.
+// Resets step counter and strip budget after a new state and records the
+// state's diagnostics on the device as the budget reference (stream-ordered,
+// no wait).
 int restart_clock(lbm_ctx *c, Slot &s) {
   HIP_TRY(lbm::launch_fill_zero(s.dev.cumq, s.lay.cumq_bytes, c->stream));
   s.step = 0;
   s.series_step.clear();
   s.series_parity.clear();
-  StatsDev st{};
-  int rc = reduce_now(c, s, &st);
-  if (rc != LBM_OK) return rc;
-  s.E0 = st.total_H;
+  HIP_TRY(lbm::launch_reduce(s.dev, s.cs.precision, c->partials, s.e0_dev, c->stream));
   return LBM_OK;
 }
 
@@ -431,17 +445,31 @@ void free_batch(lbm_ctx *c) {
   b.cavs_host = nullptr;
   b.tiles_host = nullptr;
   b.hdr_host = nullptr;
-  b.cav_cap = b.tile_cap = 0;
+  b.cav_cap = b.tile_cap = b.hdr_cap = 0;
 }
 
-// Tile list of every resident slot, FP64 cavities first.  The device
-// buffers only grow, so a captured batched graph survives membership changes.
+// Tile lists of every resident slot, grouped by cache group then precision.
+// The device buffers only grow, so a captured graph survives membership
+// changes that keep the group shape.
 int rebuild_batch(lbm_ctx *c) {
   Batch &b = c->batch;
   b.members.clear();
-  for (int prec = 0; prec < 2; ++prec)
-    for (int i = 0; i < (int)c->slots.size(); ++i)
-      if (c->slots[i].used && c->slots[i].cs.precision == prec) b.members.push_back(i);
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used) b.members.push_back(i);
+  // greedy packing in slot order: a group closes when the next cavity would
+  // overflow the capacity (a cavity larger than the capacity gets its own)
+  std::vector<int> group_of(b.members.size(), 0);
+  int ngroups = b.members.empty() ? 0 : 1;
+  size_t acc = 0;
+  for (size_t j = 0; j < b.members.size(); ++j) {
+    const size_t fp = c->slots[b.members[j]].lay.total;
+    if (acc > 0 && acc + fp > c->group_bytes) {
+      ++ngroups;
+      acc = 0;
+    }
+    acc += fp;
+    group_of[j] = ngroups - 1;
+  }
   const size_t ncav = b.members.size();
   size_t ntiles = 0;
   for (int id : b.members) {
@@ -449,91 +477,109 @@ int rebuild_batch(lbm_ctx *c) {
     ntiles += (size_t)((s.cs.nx + kBatchTileX - 1) / kBatchTileX) *
               ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
   }
+  const size_t nhdr = (size_t)std::max(ngroups, 1) * 4;
   HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
-  if (ncav > b.cav_cap || ntiles > b.tile_cap || !b.hdr_dev) {
+  if (ncav > b.cav_cap || ntiles > b.tile_cap || nhdr > b.hdr_cap) {
     free_batch(c);
     b.cav_cap = std::max<size_t>(ncav, c->slots.size());
     b.tile_cap = std::max<size_t>(ntiles * 2, 4096);
+    b.hdr_cap = std::max<size_t>(nhdr * 2, 4 * 64);
     HIP_TRY(hipMalloc(&b.cavs_dev, b.cav_cap * sizeof(CavDev)));
     HIP_TRY(hipMalloc(&b.tiles_dev, b.tile_cap * sizeof(BatchTile)));
-    HIP_TRY(hipMalloc(&b.hdr_dev, 4 * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&b.hdr_dev, b.hdr_cap * sizeof(int32_t)));
     HIP_TRY(hipHostMalloc(&b.cavs_host, b.cav_cap * sizeof(CavDev)));
     HIP_TRY(hipHostMalloc(&b.tiles_host, b.tile_cap * sizeof(BatchTile)));
-    HIP_TRY(hipHostMalloc(&b.hdr_host, 4 * sizeof(int32_t)));
+    HIP_TRY(hipHostMalloc(&b.hdr_host, b.hdr_cap * sizeof(int32_t)));
   }
+  b.group_precs.assign(ngroups, 0);
   size_t t = 0;
-  for (int prec = 0; prec < 2; ++prec) {
-    const size_t first = t;
-    for (size_t j = 0; j < ncav; ++j) {
-      const Slot &s = c->slots[b.members[j]];
-      if (s.cs.precision != prec) continue;
-      for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
-        for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
-          b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
+  for (int g = 0; g < ngroups; ++g) {
+    for (int prec = 0; prec < 2; ++prec) {
+      const size_t first = t;
+      for (size_t j = 0; j < ncav; ++j) {
+        if (group_of[j] != g) continue;
+        const Slot &s = c->slots[b.members[j]];
+        if (s.cs.precision != prec) continue;
+        for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
+          for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
+            b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
+      }
+      b.hdr_host[(g * 2 + prec) * 2] = (int32_t)first;
+      b.hdr_host[(g * 2 + prec) * 2 + 1] = (int32_t)(t - first);
+      if (t > first) b.group_precs[g] |= 1 << prec;
     }
-    b.ntiles[prec] = (int)(t - first);
-    b.hdr_host[2 * prec] = (int32_t)first;
-    b.hdr_host[2 * prec + 1] = b.ntiles[prec];
   }
   if (t > 0)
     HIP_TRY(hipMemcpyAsync(b.tiles_dev, b.tiles_host, t * sizeof(BatchTile),
                            hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host, 4 * sizeof(int32_t), hipMemcpyHostToDevice,
-                         c->stream));
+  if (ngroups > 0)
+    HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host, (size_t)ngroups * 4 * sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
   b.dirty = false;
   return LBM_OK;
 }
 
 int batch_grid(lbm_ctx *c) { return c->num_cus * 8; }
 
-hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk, int precs) {
+hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
   Batch &b = c->batch;
   hipError_t err = hipSuccess;
-  for (int k = 0; k < chunk && err == hipSuccess; ++k)
-    for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-      if (precs & (1 << prec))
-        err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev, prec, kBatchTileX,
-                                     kBatchTileRows, k, batch_grid(c), c->stream);
+  for (int g = 0; g < (int)b.group_precs.size() && err == hipSuccess; ++g)
+    for (int k = 0; k < chunk && err == hipSuccess; ++k)
+      for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
+        if (b.group_precs[g] & (1 << prec))
+          err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + (g * 2 + prec) * 2,
+                                       prec, kBatchTileX, kBatchTileRows, k, batch_grid(c),
+                                       c->stream);
   return err;
 }
 
-// Advances every resident slot by n steps with one batched launch per step
-// per precision; chunks of c->graph_chunk launches are replayed from a graph.
-int step_all(lbm_ctx *c, int64_t n) {
+// Advances slot ids[j] by n[j] steps (0 <= n[j]) with batched launches: one
+// launch per step per (cache group, precision), chunks of c->graph_chunk
+// launches replayed from a captured graph.
+int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t> &n) {
   Batch &b = c->batch;
   if (b.dirty) {
     int rc = rebuild_batch(c);
     if (rc != LBM_OK) return rc;
   }
-  if (b.members.empty()) return LBM_OK;
-  // recorded diagnostics need per-step hooks: step those slots one by one
-  for (int id : b.members)
-    if (c->slots[id].report_every > 0) {
-      for (int id2 : b.members) {
-        int rc = step_slot(c, c->slots[id2], n);
+  std::vector<int64_t> left(c->slots.size(), 0);
+  int64_t most = 0;
+  for (size_t j = 0; j < ids.size(); ++j) {
+    left[ids[j]] += n[j];
+    most = std::max(most, left[ids[j]]);
+  }
+  if (most == 0) return LBM_OK;
+  // recorded diagnostics need per-step hooks: those slots step on their own
+  bool reports = false;
+  for (int id : ids) reports = reports || c->slots[id].report_every > 0;
+  if (reports) {
+    for (size_t id = 0; id < left.size(); ++id)
+      if (left[id] > 0) {
+        int rc = step_slot(c, c->slots[id], left[id]);
         if (rc != LBM_OK) return rc;
       }
-      return LBM_OK;
-    }
-  const int precs = (b.ntiles[0] > 0 ? 1 : 0) | (b.ntiles[1] > 0 ? 2 : 0);
-  const int chunk_cap = c->graph_chunk > 0 ? c->graph_chunk : 64;
-  while (n > 0) {
-    const int chunk = (int)std::min<int64_t>(n, chunk_cap);
+    return LBM_OK;
+  }
+  const int cap = c->graph_chunk > 0 ? c->graph_chunk : 64;
+  while (most > 0) {
+    const int chunk = (int)std::min<int64_t>(most, cap);
     HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffer reuse
     for (size_t j = 0; j < b.members.size(); ++j) {
-      CavDev d = c->slots[b.members[j]].dev;
-      d.active_steps = chunk;
+      const int id = b.members[j];
+      CavDev d = c->slots[id].dev;
+      d.active_steps = (int32_t)std::min<int64_t>(left[id], chunk);
       b.cavs_host[j] = d;
     }
     HIP_TRY(hipMemcpyAsync(b.cavs_dev, b.cavs_host, b.members.size() * sizeof(CavDev),
                            hipMemcpyHostToDevice, c->stream));
     const bool use_graph = c->graph_chunk > 0 && chunk == c->graph_chunk;
     if (use_graph) {
-      if (!b.graph || b.graph_chunk != chunk || b.graph_precs != precs) {
+      if (!b.graph || b.graph_chunk != chunk || b.graph_shape != b.group_precs) {
         drop_batch_graph(c);
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t err = enqueue_batch_chunk(c, chunk, precs);
+        hipError_t err = enqueue_batch_chunk(c, chunk);
         hipError_t e2 = hipStreamEndCapture(c->stream, &g);
         if (err != hipSuccess || e2 != hipSuccess) {
           if (g) (void)hipGraphDestroy(g);
@@ -546,20 +592,33 @@ int step_all(lbm_ctx *c, int64_t n) {
           return fail(LBM_EDEVICE, "batched graph instantiate failed");
         }
         b.graph_chunk = chunk;
-        b.graph_precs = precs;
+        b.graph_shape = b.group_precs;
       }
       HIP_TRY(hipGraphLaunch(b.graph, c->stream));
     } else {
-      HIP_TRY(enqueue_batch_chunk(c, chunk, precs));
+      HIP_TRY(enqueue_batch_chunk(c, chunk));
     }
     for (int id : b.members) {
       Slot &s = c->slots[id];
-      s.step += chunk;
-      if (chunk & 1) s.dev.parity ^= 1;
+      const int64_t adv = std::min<int64_t>(left[id], chunk);
+      s.step += adv;
+      if (adv & 1) s.dev.parity ^= 1;
+      left[id] -= adv;
     }
-    n -= chunk;
+    most -= chunk;
   }
   return LBM_OK;
+}
+
+int step_all(lbm_ctx *c, int64_t n) {
+  std::vector<int> ids;
+  std::vector<int64_t> steps;
+  for (int i = 0; i < (int)c->slots.size(); ++i)
+    if (c->slots[i].used) {
+      ids.push_back(i);
+      steps.push_back(n);
+    }
+  return step_many(c, ids, steps);
 }
 
 }  // namespace
@@ -630,7 +689,7 @@ int lbm_create(lbm_ctx **out, int device, void *hip_stream, size_t hbm_budget, i
   if (rc == LBM_OK &&
       (hipMalloc(&c->partials, (size_t)lbm::kRedBlocks * 16 * sizeof(double)) != hipSuccess ||
        hipMalloc(&c->stats_dev, sizeof(StatsDev)) != hipSuccess ||
-       hipHostMalloc(&c->stats_host, sizeof(StatsDev)) != hipSuccess))
+       hipHostMalloc(&c->stats_host, 2 * sizeof(StatsDev)) != hipSuccess))
     rc = fail(LBM_ENOMEM, "cannot allocate reduction scratch");
   if (rc != LBM_OK) {
     lbm_destroy(c);
@@ -697,6 +756,7 @@ int lbm_set_case(lbm_ctx *c, const lbm_case *cs, void *dev_buf, size_t buf_bytes
   s.base = base;
   s.owned = owned;
   s.dev = make_dev(cs, lat, lay, base);
+  s.e0_dev = reinterpret_cast<StatsDev *>(static_cast<char *>(base) + lay.aux_off);
   c->used += lay.total;
   c->batch.dirty = true;
   hipError_t e = lbm::launch_init(s.dev, cs->precision, cs->init, cs->T0, cs->gauss_amp,
@@ -741,15 +801,39 @@ int lbm_step(lbm_ctx *c, int slot, int64_t nsteps) {
   return step_slot(c, c->slots[slot], nsteps);
 }
 
+int lbm_step_many(lbm_ctx *c, int count, const int32_t *slots, const int64_t *nsteps) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (count < 0 || (count > 0 && (!slots || !nsteps))) return fail(LBM_EINVAL, "bad slot list");
+  std::vector<int> ids(count);
+  std::vector<int64_t> n(count);
+  for (int j = 0; j < count; ++j) {
+    int rc = check_slot(c, slots[j]);
+    if (rc != LBM_OK) return rc;
+    if (nsteps[j] < 0) return fail(LBM_EINVAL, "negative step count");
+    ids[j] = slots[j];
+    n[j] = nsteps[j];
+  }
+  return step_many(c, ids, n);
+}
+
+int lbm_set_group_bytes(lbm_ctx *c, size_t bytes) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (bytes < (size_t(1) << 20)) return fail(LBM_EINVAL, "group capacity below 1 MiB");
+  c->group_bytes = bytes;
+  c->batch.dirty = true;
+  return LBM_OK;
+}
+
 int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out) {
   int rc = check_slot(c, slot);
   if (rc != LBM_OK) return rc;
   if (!out) return fail(LBM_EINVAL, "output is NULL");
   Slot &s = c->slots[slot];
   StatsDev d{};
-  rc = reduce_now(c, s, &d);
+  double e0 = 0.0;
+  rc = reduce_now(c, s, &d, &e0);
   if (rc != LBM_OK) return rc;
-  fill_stats(s, d, s.step, s.dev.parity, out);
+  fill_stats(s, d, e0, s.step, s.dev.parity, out);
   if (!out->finite) return fail(LBM_EUNSTABLE, "populations are not finite");
   return LBM_OK;
 }
@@ -808,9 +892,12 @@ int lbm_series(lbm_ctx *c, int slot, lbm_stats *host, int32_t max, int32_t *coun
   *count = k;
   if (k == 0) return LBM_OK;
   std::vector<StatsDev> tmp(k);
+  StatsDev e0{};
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(tmp.data(), s.series, k * sizeof(StatsDev), hipMemcpyDeviceToHost));
-  for (int32_t j = 0; j < k; ++j) fill_stats(s, tmp[j], s.series_step[j], s.series_parity[j], host + j);
+  HIP_TRY(hipMemcpy(&e0, s.e0_dev, sizeof(StatsDev), hipMemcpyDeviceToHost));
+  for (int32_t j = 0; j < k; ++j)
+    fill_stats(s, tmp[j], e0.total_H, s.series_step[j], s.series_parity[j], host + j);
   return LBM_OK;
 }
 

@@ -84,10 +84,11 @@ def test_footprint_layout():
         for pat, lattices in ((P.LBM_PATTERN_AA, 1), (P.LBM_PATTERN_AB, 2)):
             c = P.make_case(large_cavity(), precision=prec, pattern=pat)
             pops = 18 * 2048 * 1024 * elem
-            assert P.lbm_footprint(c) == lattices * pops + 2048 * 8
+            # populations, per-column strip flux, one 256-byte block of diagnostics
+            assert P.lbm_footprint(c) == lattices * pops + 2048 * 8 + 256
     # ragged width: rows padded to a 64-cell pitch
     c = P.make_case(cavity(100, 10))
-    assert P.lbm_footprint(c) == (18 * 128 * 10 * 8 + 255) // 256 * 256 + 1024
+    assert P.lbm_footprint(c) == (18 * 128 * 10 * 8 + 255) // 256 * 256 + 1024 + 256
 
 
 def test_create_without_gpu_fails_cleanly():
