@@ -67,10 +67,11 @@ constexpr int kRedThreads = 256;
 hipError_t launch_init(const CavDev &c, int precision, int mode, double T0, double amp,
                        double sigma, hipStream_t s);
 hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
-// hdr_dev: {first tile, tile count} for FP64 then for FP32 (4 ints).
+// hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
+// entries (the kernel ignores a header that points outside them).
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
-                             const int32_t *hdr_dev, int precision, int tile_bx, int tile_rows,
-                             int launch_index, int grid, hipStream_t s);
+                             const int32_t *hdr_dev, int tile_cap, int precision, int tile_bx,
+                             int tile_rows, int launch_index, int grid, hipStream_t s);
 hipError_t launch_reduce(const CavDev &c, int precision, double *partials, StatsDev *out,
                          hipStream_t s);
 hipError_t launch_fields(const CavDev &c, int precision, uint32_t mask, double *out,

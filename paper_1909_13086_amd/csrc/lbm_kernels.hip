@@ -356,8 +356,10 @@ template <typename S, typename R>
 __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ cavs,
                                                     const BatchTile *__restrict__ tiles,
                                                     const int32_t *__restrict__ hdr,
-                                                    int tile_rows, int launch_index) {
+                                                    int tile_cap, int tile_rows,
+                                                    int launch_index) {
   const int first = hdr[0], ntiles = hdr[1];
+  if (first < 0 || ntiles <= 0 || first > tile_cap - ntiles) return;
   const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
   const int nbx = (gridDim.x - xcd + kXcds - 1) / kXcds;
   const int t0 = (int)((int64_t)ntiles * xcd / kXcds);
@@ -691,16 +693,16 @@ hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hip
 }
 
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
-                             const int32_t *hdr_dev, int precision, int tile_bx, int tile_rows,
-                             int launch_index, int grid, hipStream_t s) {
+                             const int32_t *hdr_dev, int tile_cap, int precision, int tile_bx,
+                             int tile_rows, int launch_index, int grid, hipStream_t s) {
   const int by = 256 / tile_bx;
   const dim3 block(tile_bx, by < 1 ? 1 : by);
   if (precision == 0)
     hipLaunchKernelGGL((k_step_batch<double, double>), dim3(grid), block, 0, s, cavs_dev,
-                       tiles_dev, hdr_dev, tile_rows, launch_index);
+                       tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
   else
     hipLaunchKernelGGL((k_step_batch<float, float>), dim3(grid), block, 0, s, cavs_dev,
-                       tiles_dev, hdr_dev + 2, tile_rows, launch_index);
+                       tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
   return hipGetLastError();
 }
 

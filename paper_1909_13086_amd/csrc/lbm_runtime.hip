@@ -490,6 +490,7 @@ int rebuild_batch(lbm_ctx *c) {
     HIP_TRY(hipHostMalloc(&b.cavs_host, b.cav_cap * sizeof(CavDev)));
     HIP_TRY(hipHostMalloc(&b.tiles_host, b.tile_cap * sizeof(BatchTile)));
     HIP_TRY(hipHostMalloc(&b.hdr_host, b.hdr_cap * sizeof(int32_t)));
+    HIP_TRY(lbm::launch_fill_zero(b.hdr_dev, b.hdr_cap * sizeof(int32_t), c->stream));
   }
   b.group_precs.assign(ngroups, 0);
   size_t t = 0;
@@ -529,8 +530,8 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
         if (b.group_precs[g] & (1 << prec))
           err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + (g * 2 + prec) * 2,
-                                       prec, kBatchTileX, kBatchTileRows, k, batch_grid(c),
-                                       c->stream);
+                                       (int)b.tile_cap, prec, kBatchTileX, kBatchTileRows, k,
+                                       batch_grid(c), c->stream);
   return err;
 }
 
