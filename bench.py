@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_LU = {0: 288, 1: 144}  # 18 populations read + written, FP64 / FP32
 REPORT_EVERY = 100
-KERNEL_SRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc", "lbm_kernels.hip")
+# sources of the step kernel: a change to either invalidates stored counter traffic
+KERNEL_SRC = [os.path.join(ROOT, "paper_1909_13086_amd", "csrc", f) for f in ("lbm_device.h", "lbm_step.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md")
 
 
@@ -36,8 +37,11 @@ def log(msg):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -203,7 +207,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--graph-chunk", type=int, default=0)
-    ap.add_argument("--tile", default="", help="bx,by,cpl,xcd for the FP64 step kernel")
+    ap.add_argument("--tile", default="", help="bx,by,cpl,flags for the FP64 step kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")

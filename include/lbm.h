@@ -188,12 +188,16 @@ int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n);
 
 /* ---- execution control ---------------------------------------------------- */
 
+enum {
+  LBM_LAUNCH_XCD_BANDS = 1,  /* each of the 8 XCDs gets a contiguous band of tiles */
+  LBM_LAUNCH_NONTEMPORAL = 2 /* population loads/stores bypass cache retention */
+};
 /* Tile of the single-cavity step kernels for a precision: bx threads along x
  * (multiple of 64), by rows per block (bx*by <= 256), cpl rows per lane (1, 2
- * or 4), xcd_remap (1 = give each of the 8 XCDs a contiguous band of tiles).
- * Results do not depend on the tile. */
-int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int xcd_remap);
-int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *xcd_remap);
+ * or 4) and LBM_LAUNCH_* flags.  Default 256, 1, 1, LBM_LAUNCH_XCD_BANDS.
+ * Results do not depend on the tile or the flags. */
+int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags);
+int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
 int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
 /* Times the candidate tiles on a scratch cavity of the given size and

@@ -22,6 +22,7 @@ LBM_INIT_SOLID_AT_TM, LBM_INIT_LIQUID_T0, LBM_INIT_GAUSSIAN = 0, 1, 2
 LBM_FIELD_T, LBM_FIELD_FL, LBM_FIELD_H, LBM_FIELD_UX, LBM_FIELD_UY, LBM_FIELD_RHO = 1, 2, 4, 8, 16, 32
 FIELD_NAMES = ("T", "fl", "H", "ux", "uy", "rho")
 LBM_ALL = -1
+LBM_LAUNCH_XCD_BANDS, LBM_LAUNCH_NONTEMPORAL = 1, 2
 
 # Names exported by include/lbm.h and include/lbm_serve.h.
 EXPORTS = (
@@ -270,8 +271,8 @@ def lbm_state_save(ctx, slot, nx, ny):
 
 # ---- execution control --------------------------------------------------------
 
-def lbm_set_launch(ctx, precision, bx, by, cpl, xcd_remap=1):
-    _check(lib().lbm_set_launch(ctx, int(precision), int(bx), int(by), int(cpl), int(xcd_remap)))
+def lbm_set_launch(ctx, precision, bx, by, cpl, flags=LBM_LAUNCH_XCD_BANDS):
+    _check(lib().lbm_set_launch(ctx, int(precision), int(bx), int(by), int(cpl), int(flags)))
 
 
 def lbm_get_launch(ctx, precision):

@@ -92,8 +92,8 @@ class Context:
     def series(self, slot):
         return L.lbm_series(self.h, slot)
 
-    def set_launch(self, precision, bx, by, cpl, xcd_remap=1):
-        L.lbm_set_launch(self.h, precision, bx, by, cpl, xcd_remap)
+    def set_launch(self, precision, bx, by, cpl, flags=L.LBM_LAUNCH_XCD_BANDS):
+        L.lbm_set_launch(self.h, precision, bx, by, cpl, flags)
 
     def set_graph_chunk(self, chunk):
         L.lbm_set_graph_chunk(self.h, chunk)

@@ -1,0 +1,62 @@
+// Batched step kernel: one launch advances many cavities of uneven size by one
+// time step each, from a tile list in device memory.
+#include "lbm_device.h"
+
+namespace lbm {
+namespace {
+
+using namespace dev;
+
+// Batched step over tiles of many cavities.  hdr holds {first tile, tile
+// count} of this launch, read on the device so that a captured launch stays
+// valid when cavities join or leave.  The tile list is cut into 8 contiguous
+// bands, one per XCD (workgroups are dispatched round-robin over the XCDs),
+// and each XCD's workgroups stride through its band, so neighbouring tiles
+// share that XCD's L2.  Cavity j advances in this launch only while
+// launch_index < active_steps(j); its storage parity is its chunk-start
+// parity flipped by the launch index.
+template <typename S, typename R>
+__global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ cavs,
+                                                    const BatchTile *__restrict__ tiles,
+                                                    const int32_t *__restrict__ hdr,
+                                                    int tile_cap, int tile_rows,
+                                                    int launch_index) {
+  const int first = hdr[0], ntiles = hdr[1];
+  if (first < 0 || ntiles <= 0 || first > tile_cap - ntiles) return;
+  const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
+  const int nbx = (gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int t0 = (int)((int64_t)ntiles * xcd / kXcds);
+  const int t1 = (int)((int64_t)ntiles * (xcd + 1) / kXcds);
+  for (int t = t0 + lb; t < t1; t += nbx) {
+    const BatchTile tile = tiles[first + t];
+    CavDev c = cavs[tile.cav];
+    if (launch_index >= c.active_steps) continue;
+    c.parity ^= (launch_index & 1);
+    const Coef<R> k(c);
+    const int mode = storage_mode(c);
+    const int x = tile.x0 + threadIdx.x;
+    if (x >= c.nx) continue;
+    for (int r = threadIdx.y; r < tile_rows; r += blockDim.y) {
+      const int y = tile.y0 + r;
+      if (y < c.ny) update_cell<S, R>(c, k, mode, x, y);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
+                             const int32_t *hdr_dev, int tile_cap, int precision, int tile_bx,
+                             int tile_rows, int launch_index, int grid, hipStream_t s) {
+  const int by = 256 / tile_bx;
+  const dim3 block(tile_bx, by < 1 ? 1 : by);
+  if (precision == 0)
+    hipLaunchKernelGGL((k_step_batch<double, double>), dim3(grid), block, 0, s, cavs_dev,
+                       tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+  else
+    hipLaunchKernelGGL((k_step_batch<float, float>), dim3(grid), block, 0, s, cavs_dev,
+                       tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

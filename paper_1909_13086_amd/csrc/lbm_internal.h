@@ -45,7 +45,9 @@ struct BatchTile {
 };
 
 struct LaunchCfg {
-  int bx = 256, by = 1, cpl = 1, xcd = 1;
+  int bx = 256, by = 1, cpl = 1;
+  int xcd = 1;  // contiguous tile bands per XCD
+  int nt = 0;   // non-temporal population loads and stores
 };
 
 // Accumulators of one reduction, FP64.

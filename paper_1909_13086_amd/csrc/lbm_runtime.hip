@@ -937,7 +937,7 @@ int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n) {
   return LBM_OK;
 }
 
-int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int xcd_remap) {
+int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
   if (bx < 64 || bx % 64 != 0 || by < 1 || bx * by > 256 || (cpl != 1 && cpl != 2 && cpl != 4))
@@ -946,19 +946,20 @@ int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int xcd_r
   L.bx = bx;
   L.by = by;
   L.cpl = cpl;
-  L.xcd = xcd_remap ? 1 : 0;
+  L.xcd = (flags & LBM_LAUNCH_XCD_BANDS) ? 1 : 0;
+  L.nt = (flags & LBM_LAUNCH_NONTEMPORAL) ? 1 : 0;
   for (auto &s : c->slots) drop_graphs(s);
   return LBM_OK;
 }
 
-int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *xcd_remap) {
-  if (!c || !bx || !by || !cpl || !xcd_remap) return fail(LBM_EINVAL, "NULL argument");
+int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags) {
+  if (!c || !bx || !by || !cpl || !flags) return fail(LBM_EINVAL, "NULL argument");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
   const LaunchCfg &L = c->launch[precision];
   *bx = L.bx;
   *by = L.by;
   *cpl = L.cpl;
-  *xcd_remap = L.xcd;
+  *flags = (L.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (L.nt ? LBM_LAUNCH_NONTEMPORAL : 0);
   return LBM_OK;
 }
 
@@ -1008,7 +1009,7 @@ std::string size_class(int precision, int nx, int ny) {
          "x" + std::to_string(p2(ny));
 }
 
-// The cache is a flat JSON object {"<class>": [bx, by, cpl, xcd, us_per_step], ...}.
+// The cache is a flat JSON object {"<class>": [bx, by, cpl, flags, us_per_step], ...}.
 std::map<std::string, std::vector<double>> read_cache(const char *path) {
   std::map<std::string, std::vector<double>> m;
   if (!path) return m;
@@ -1099,12 +1100,13 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   const int reps = 10;
   for (const auto &sh : shapes) {
     for (int cpl : cpls) {
-      for (int xcd = 0; xcd < 2 && rc == LBM_OK; ++xcd) {
+      for (int flags = 0; flags < 4 && rc == LBM_OK; ++flags) {
         LaunchCfg cfg;
         cfg.bx = sh[0];
         cfg.by = sh[1];
         cfg.cpl = cpl;
-        cfg.xcd = xcd;
+        cfg.xcd = flags & LBM_LAUNCH_XCD_BANDS ? 1 : 0;
+        cfg.nt = flags & LBM_LAUNCH_NONTEMPORAL ? 1 : 0;
         hipError_t e = hipSuccess;
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
           e = lbm::launch_step(d, precision, cfg, c->stream);
@@ -1138,8 +1140,10 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
     c->launch[precision] = saved;
     return rc;
   }
-  cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best.xcd,
+  const int best_flags =
+      (best.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (best.nt ? LBM_LAUNCH_NONTEMPORAL : 0);
+  cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best_flags,
                 1000.0 * best_ms / reps};
   write_cache(cache_path, cache);
-  return lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best.xcd);
+  return lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best_flags);
 }

@@ -1,0 +1,56 @@
+// Single-cavity step kernel: one launch advances one cavity by one time step
+// (A-A parity or two-lattice direction from the cavity descriptor).
+#include "lbm_device.h"
+
+namespace lbm {
+namespace {
+
+using namespace dev;
+
+// Tile of bx x (by*CPL) cells per workgroup; each lane updates CPL cells of
+// one column.  With xcd set, consecutive tiles go to one XCD (contiguous bands
+// per XCD share its L2 at tile edges).
+template <typename S, typename R, int CPL, bool NT>
+__global__ __launch_bounds__(256) void k_step(CavDev c, int tiles_x, int xcd) {
+  const int b = xcd ? xcd_band(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int tx = b % tiles_x, ty = b / tiles_x;
+  const int x = tx * blockDim.x + threadIdx.x;
+  const int ybase = ty * blockDim.y * CPL + threadIdx.y;
+  const Coef<R> k(c);
+  const int mode = storage_mode(c);
+  if (x >= c.nx) return;
+#pragma unroll
+  for (int r = 0; r < CPL; ++r) {
+    const int y = ybase + r * blockDim.y;
+    if (y < c.ny) update_cell<S, R, NT>(c, k, mode, x, y);
+  }
+}
+
+template <typename S, typename R, bool NT>
+hipError_t dispatch_cpl(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
+  const int tiles_x = (c.nx + cfg.bx - 1) / cfg.bx;
+  const int rows = cfg.by * cfg.cpl;
+  const int tiles_y = (c.ny + rows - 1) / rows;
+  const dim3 block(cfg.bx, cfg.by);
+  const dim3 grid(tiles_x * tiles_y);
+  switch (cfg.cpl) {
+    case 1: hipLaunchKernelGGL((k_step<S, R, 1, NT>), grid, block, 0, s, c, tiles_x, cfg.xcd); break;
+    case 2: hipLaunchKernelGGL((k_step<S, R, 2, NT>), grid, block, 0, s, c, tiles_x, cfg.xcd); break;
+    case 4: hipLaunchKernelGGL((k_step<S, R, 4, NT>), grid, block, 0, s, c, tiles_x, cfg.xcd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename S, typename R>
+hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
+  return cfg.nt ? dispatch_cpl<S, R, true>(c, cfg, s) : dispatch_cpl<S, R, false>(c, cfg, s);
+}
+
+}  // namespace
+
+hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {
+  return precision == 0 ? dispatch<double, double>(c, cfg, s) : dispatch<float, float>(c, cfg, s);
+}
+
+}  // namespace lbm

@@ -29,7 +29,7 @@ def _trace(P):
         nx, ny = sizes[k % len(sizes)]
         prec = P.LBM_FP32_SHIFTED if k % 2 else P.LBM_FP64
         case = dict(cavity(nx, ny, Ra=10 ** (5 + (k % 3)), heater_center=0.2 + 0.05 * k), precision=prec)
-        out.append((case, 150 + 37 * k, 0.01 * k))
+        out.append((case, 1500 + 97 * k, 0.0005 * k))
     return out
 
 
