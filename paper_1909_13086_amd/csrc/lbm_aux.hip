@@ -27,7 +27,7 @@ __global__ void k_init(CavDev c, int mode, double T0, double amp, double sigma) 
   const double fl = T > c.Tm ? 1.0 : 0.0;
   const double th = T - c.Tm;
   const double dH = c.Cp * th + fl * c.latent;
-  const int64_t idx = (int64_t)y * c.pitch + x;
+  const int64_t idx = cell_base(c, x, y);
   S *P = static_cast<S *>(c.pop[0]);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -43,7 +43,7 @@ __global__ void k_load(CavDev c, const double *__restrict__ f, const double *__r
   const int y = blockIdx.y;
   if (x >= c.nx || y >= c.ny) return;
   const int64_t n = (int64_t)c.nx * c.ny, h = (int64_t)y * c.nx + x;
-  const int64_t idx = (int64_t)y * c.pitch + x;
+  const int64_t idx = cell_base(c, x, y);
   S *P = static_cast<S *>(c.pop[0]);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -59,7 +59,7 @@ template <typename S>
 __device__ __forceinline__ void load_pre(const CavDev &c, int x, int y, double (&f)[kQ],
                                          double (&g)[kQ]) {
   using R = S;
-  const int64_t idx = (int64_t)y * c.pitch + x;
+  const int64_t idx = cell_base(c, x, y);
   R fr[kQ], gr[kQ];
   if (c.pattern == 1) {
     load_natural<S, R>(static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]), c.plane, idx, fr,

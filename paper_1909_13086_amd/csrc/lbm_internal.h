@@ -25,7 +25,7 @@ struct CavDev {
   int32_t pattern;     // 0 in place (A-A), 1 two lattices
   int32_t active_steps; // batched launch: launches of the current chunk that advance it
   int32_t pad_;
-  int64_t plane;       // elements per population plane = pitch * ny
+  int64_t plane;       // elements between consecutive population planes of a cell
   // relaxation rates of Eq. (2)
   double k0g, k1g, k2g, k0f, k1f, k2f;
   double Cp, inv_Cp, latent, inv_latent, rho0, inv_rho0;

@@ -275,7 +275,7 @@ CavDev make_dev(const lbm_case *cs, const lbm_lattice &lat, const Layout &lay, v
   d.parity = 0;
   d.pattern = cs->pattern;
   d.active_steps = 0;
-  d.plane = (int64_t)lat.pitch * cs->ny;
+  d.plane = lbm::kWave;  // blocked layout: planes of a 64-cell chunk are 64 elements apart
   d.k0g = lat.k0_g;
   d.k1g = lat.k1_g;
   d.k2g = lat.k2_g;
