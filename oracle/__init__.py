@@ -143,8 +143,11 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().or_destroy(h)
+        if h and _LIB is not None:
+            try:
+                _LIB.or_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def init_solid(self):

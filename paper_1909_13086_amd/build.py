@@ -2,7 +2,9 @@
 
 Every HIP translation unit is built for gfx950 only, with packed-FP32 vector
 instructions switched off (``-packed-fp32-ops``): the compiler would otherwise
-form v_pk_* FP32 operations from plain float code.
+form v_pk_* FP32 operations from plain float code.  Multiply-adds are fused
+only within one source expression (``-ffp-contract=on``), so the same update
+inlined into different kernels (single cavity, batched) rounds identically.
 """
 import os
 import shutil
@@ -18,7 +20,7 @@ SOURCES = ["lbm_step.hip", "lbm_batch.hip", "lbm_aux.hip", "lbm_runtime.hip", "l
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
