@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
+    ap.add_argument("--only", choices=["fp32", "batched", "serving"], default="",
+                    help="run one variant alone (for profiling) and print its result")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -221,6 +223,17 @@ def main():
         calib_copy(args.calib_copy)
         return
     import paper_1909_13086_amd as P
+
+    if args.only:
+        if args.only == "fp32":
+            res = fp32_variant(P, max(500, args.steps // 4))
+        elif args.only == "batched":
+            res = batched_variant(P, args.steps)
+        else:
+            from paper_1909_13086_amd import serve
+            res = serve.bench_serving(P)
+        print(json.dumps({"only": args.only, **res}), flush=True)
+        return
 
     m = main_workload(P, args)
     mlups = m["cells"] * args.steps / (m["ms"] * 1e-3) / 1e6
