@@ -96,6 +96,7 @@ def lib():
         L.or_feq.argtypes = [ctypes.c_double] * 4 + [_dp]
         L.or_collide_cell.argtypes = [ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -218,3 +219,8 @@ def collide_cell(params, f, g):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_threads(n):
+    """Threads of the row loops; 1-D columns run fastest on one."""
+    lib().or_set_threads(int(n))

@@ -504,6 +504,14 @@ void or_get_stats(const or_state *st, or_stats *out) {
   out->finite = finite;
 }
 
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

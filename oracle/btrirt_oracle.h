@@ -108,6 +108,7 @@ void or_collide_cell(const or_params *p, const double f[OR_Q], const double g[OR
                      double fout[OR_Q], double gout[OR_Q], double macro[6]);
 
 int or_num_threads(void);
+void or_set_threads(int n); /* OpenMP threads for the row loops (results do not depend on it) */
 
 #ifdef __cplusplus
 }
