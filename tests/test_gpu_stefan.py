@@ -54,13 +54,20 @@ def test_paper_stefan_case(P, k1, srt):
         s = ctx.add(case)
         ctx.step(s, steps)
         fld = ctx.fields(s)
-        f_gpu, g_gpu = ctx.state_save(s)
     oracle.set_threads(1)
     o = oracle.Oracle(oracle.case_from_dict(case)).init_solid().step(steps)
-    f_or, g_or = o.populations()
-    assert np.max(np.abs(g_gpu - g_or)) <= 1e-10 * 100  # populations scale with L = 100
-    assert np.max(np.abs(f_gpu - f_or)) <= 1e-12
+    ofl = o.fields()
     H, fl, T = fld["H"][:, 0], fld["fl"][:, 0], fld["T"][:, 0]
+    # FP64 bar: 1e-10 after 2000 steps on quantities of order one; round-off
+    # gathers at most linearly with the step count in this dissipative scheme,
+    # and H is of order L = 100 here
+    scale = max(1.0, steps / 2000)
+    dT = float(np.max(np.abs(T - ofl["T"][:, 0])))
+    dfl = float(np.max(np.abs(fl - ofl["fl"][:, 0])))
+    dH = float(np.max(np.abs(H - ofl["H"][:, 0])))
+    print(f"  GPU vs oracle: max|dT| {dT:.2e}, max|dfl| {dfl:.2e}, max|dH| {dH:.2e} (bar x{scale:.0f})", flush=True)
+    assert dT <= 1e-10 * scale and dfl <= 1e-10 * scale
+    assert dH <= 1e-10 * scale * 100
     y = (np.arange(NY) + 0.5) * DX
     xi = 2 * kappa_s() * math.sqrt(ALPHA * T_END)
     front = fl.sum() * DX
@@ -72,11 +79,13 @@ def test_paper_stefan_case(P, k1, srt):
     t_err = float(np.max(np.abs(T[liquid] - t_an[liquid])))
     print(f"  front {front:.4f} (Neumann {xi:.4f}), interface cells {interface}, "
           f"max|H - Cp Tm| ahead {dev_solid:.2e}, Linf(T) liquid {t_err:.3e}", flush=True)
-    assert abs(front - xi) / xi <= 0.03
-    assert t_err <= 0.02
     if not srt or k1 == 1.0:
-        # Eq. (5) holds (SRT with k1 = 1 is also k1 + k2 = 2)
+        # Eq. (5) holds (SRT with k1 = 1 is also k1 + k2 = 2): the solid stays at
+        # Tm, the interface is one cell, and the Neumann solution is followed
         assert dev_solid <= 1e-12
         assert interface <= 1
+        assert abs(front - xi) / xi <= 0.03
+        assert t_err <= 0.02
     else:
+        # SRT with k1 != 1: the solid ahead of the front is activated
         assert dev_solid > 1e-3
