@@ -69,6 +69,32 @@ class Stats(ctypes.Structure):
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
+def load_library(path):
+    """A configured handle on an oracle shared library at `path`."""
+    L = ctypes.CDLL(path)
+    L.or_derive.argtypes = [ctypes.POINTER(Case), ctypes.POINTER(Params)]
+    L.or_create.argtypes = [ctypes.POINTER(Case)]
+    L.or_create.restype = ctypes.c_void_p
+    L.or_destroy.argtypes = [ctypes.c_void_p]
+    L.or_get_params.argtypes = [ctypes.c_void_p]
+    L.or_get_params.restype = ctypes.POINTER(Params)
+    L.or_init_solid.argtypes = [ctypes.c_void_p]
+    L.or_init_liquid.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    L.or_init_gaussian.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.or_set_populations.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.or_get_populations.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    L.or_fields.argtypes = [ctypes.c_void_p] + [_dp] * 6
+    L.or_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stats)]
+    L.or_enthalpy_map.argtypes = [ctypes.c_double] * 4 + [_dp, _dp]
+    L.or_geq.argtypes = [ctypes.c_double] * 5 + [_dp]
+    L.or_feq.argtypes = [ctypes.c_double] * 4 + [_dp]
+    L.or_collide_cell.argtypes = [ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp]
+    L.or_num_threads.restype = ctypes.c_int
+    L.or_set_threads.argtypes = [ctypes.c_int]
+    return L
+
+
 def lib():
     """Load (building first if needed) the oracle shared library."""
     global _LIB
@@ -76,28 +102,7 @@ def lib():
         path = os.path.join(_HERE, "libbtrirt_oracle.so")
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
-        L = ctypes.CDLL(path)
-        L.or_derive.argtypes = [ctypes.POINTER(Case), ctypes.POINTER(Params)]
-        L.or_create.argtypes = [ctypes.POINTER(Case)]
-        L.or_create.restype = ctypes.c_void_p
-        L.or_destroy.argtypes = [ctypes.c_void_p]
-        L.or_get_params.argtypes = [ctypes.c_void_p]
-        L.or_get_params.restype = ctypes.POINTER(Params)
-        L.or_init_solid.argtypes = [ctypes.c_void_p]
-        L.or_init_liquid.argtypes = [ctypes.c_void_p, ctypes.c_double]
-        L.or_init_gaussian.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double]
-        L.or_set_populations.argtypes = [ctypes.c_void_p, _dp, _dp]
-        L.or_get_populations.argtypes = [ctypes.c_void_p, _dp, _dp]
-        L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
-        L.or_fields.argtypes = [ctypes.c_void_p] + [_dp] * 6
-        L.or_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stats)]
-        L.or_enthalpy_map.argtypes = [ctypes.c_double] * 4 + [_dp, _dp]
-        L.or_geq.argtypes = [ctypes.c_double] * 5 + [_dp]
-        L.or_feq.argtypes = [ctypes.c_double] * 4 + [_dp]
-        L.or_collide_cell.argtypes = [ctypes.POINTER(Params), _dp, _dp, _dp, _dp, _dp]
-        L.or_num_threads.restype = ctypes.c_int
-        L.or_set_threads.argtypes = [ctypes.c_int]
-        _LIB = L
+        _LIB = load_library(path)
     return _LIB
 
 
