@@ -186,6 +186,17 @@ int lbm_series(lbm_ctx *c, int slot, lbm_stats *host, int32_t max, int32_t *coun
 int lbm_state_load(lbm_ctx *c, int slot, const double *f, const double *g, size_t n);
 int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n);
 
+/* Checkpoint / resume.  A checkpoint is the slot's device region exactly as
+ * stored (populations in their precision, layout and storage parity, the
+ * per-column strip flux, the diagnostics at load) behind a header with the
+ * case, the step counter and the parity; lbm_checkpoint_bytes gives its size
+ * (0 for an unused slot).  Loading needs a slot of the same size, precision
+ * and pattern; the restored slot takes the checkpoint's case, and stepping on
+ * from it reproduces the uninterrupted run bit for bit.  Both block. */
+size_t lbm_checkpoint_bytes(lbm_ctx *c, int slot);
+int lbm_checkpoint_save(lbm_ctx *c, int slot, void *host, size_t n);
+int lbm_checkpoint_load(lbm_ctx *c, int slot, const void *host, size_t n);
+
 /* ---- execution control ---------------------------------------------------- */
 
 enum {

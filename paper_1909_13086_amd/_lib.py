@@ -31,6 +31,7 @@ EXPORTS = (
     "lbm_fields", "lbm_set_report", "lbm_series", "lbm_state_load", "lbm_state_save",
     "lbm_set_launch", "lbm_get_launch", "lbm_set_graph_chunk", "lbm_autotune", "lbm_sync",
     "lbm_stream", "lbm_slot_info", "lbm_step_many", "lbm_set_group_bytes",
+    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
     "lbm_server_request", "lbm_server_summary",
 )
@@ -143,6 +144,9 @@ def lib():
             "lbm_set_graph_chunk": (ctypes.c_int, [vp, ctypes.c_int]),
             "lbm_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p]),
             "lbm_sync": (ctypes.c_int, [vp]),
+            "lbm_checkpoint_bytes": (ctypes.c_size_t, [vp, ctypes.c_int]),
+            "lbm_checkpoint_save": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t]),
+            "lbm_checkpoint_load": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t]),
             "lbm_stream": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
             "lbm_slot_info": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)]),
@@ -267,6 +271,21 @@ def lbm_state_save(ctx, slot, nx, ny):
     g = np.empty((9, ny, nx))
     _check(lib().lbm_state_save(ctx, int(slot), _ptr(f), _ptr(g), f.size))
     return f, g
+
+
+def lbm_checkpoint_save(ctx, slot):
+    """Checkpoint of a slot as bytes."""
+    n = int(lib().lbm_checkpoint_bytes(ctx, int(slot)))
+    if n == 0:
+        raise LbmError(LBM_ESTATE, f"slot {slot} is not in use")
+    buf = ctypes.create_string_buffer(n)
+    _check(lib().lbm_checkpoint_save(ctx, int(slot), ctypes.cast(buf, ctypes.c_void_p), n))
+    return buf.raw
+
+
+def lbm_checkpoint_load(ctx, slot, blob):
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib().lbm_checkpoint_load(ctx, int(slot), ctypes.cast(buf, ctypes.c_void_p), len(blob)))
 
 
 # ---- execution control --------------------------------------------------------

@@ -86,6 +86,12 @@ class Context:
         nx, ny = self._shape[slot]
         return L.lbm_state_save(self.h, slot, nx, ny)
 
+    def checkpoint(self, slot):
+        return L.lbm_checkpoint_save(self.h, slot)
+
+    def restore(self, slot, blob):
+        L.lbm_checkpoint_load(self.h, slot, blob)
+
     def set_report(self, slot, every, capacity):
         L.lbm_set_report(self.h, slot, every, capacity)
 

@@ -1147,3 +1147,87 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   write_cache(cache_path, cache);
   return lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best_flags);
 }
+
+// ---------------------------------------------------------------------------
+// checkpoints: the slot's device region as stored, behind a small header
+
+namespace {
+
+struct CheckpointHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t precision, pattern, parity, pad;
+  int64_t step;
+  uint64_t region_bytes;
+  lbm_case cs;
+};
+
+constexpr char kMagic[8] = {'B', 'T', 'R', 'I', 'R', 'T', 'C', 'K'};
+
+}  // namespace
+
+extern "C" size_t lbm_checkpoint_bytes(lbm_ctx *c, int slot) {
+  if (check_slot(c, slot) != LBM_OK) return 0;
+  return sizeof(CheckpointHeader) + c->slots[slot].lay.total;
+}
+
+extern "C" int lbm_checkpoint_save(lbm_ctx *c, int slot, void *host, size_t n) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  const size_t need = sizeof(CheckpointHeader) + s.lay.total;
+  if (!host || n < need) return fail(LBM_EINVAL, "checkpoint buffer holds fewer than " + std::to_string(need) + " bytes");
+  CheckpointHeader h{};
+  std::memcpy(h.magic, kMagic, sizeof(kMagic));
+  h.version = 1;
+  h.header_bytes = sizeof(CheckpointHeader);
+  h.precision = s.cs.precision;
+  h.pattern = s.cs.pattern;
+  h.parity = s.dev.parity;
+  h.step = s.step;
+  h.region_bytes = s.lay.total;
+  h.cs = s.cs;
+  std::memcpy(host, &h, sizeof(h));
+  HIP_TRY(hipMemcpyAsync(static_cast<char *>(host) + sizeof(h), s.base, s.lay.total,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_checkpoint_load(lbm_ctx *c, int slot, const void *host, size_t n) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  CheckpointHeader h{};
+  if (!host || n < sizeof(h)) return fail(LBM_EINVAL, "checkpoint too short");
+  std::memcpy(&h, host, sizeof(h));
+  if (std::memcmp(h.magic, kMagic, sizeof(kMagic)) != 0 || h.version != 1 ||
+      h.header_bytes != sizeof(h))
+    return fail(LBM_EINVAL, "not a checkpoint of this library version");
+  if (h.cs.nx != s.cs.nx || h.cs.ny != s.cs.ny || h.precision != s.cs.precision ||
+      h.pattern != s.cs.pattern || h.region_bytes != s.lay.total)
+    return fail(LBM_EINVAL, "checkpoint was taken from a cavity of another size, precision or pattern");
+  if (n < sizeof(h) + h.region_bytes) return fail(LBM_EINVAL, "checkpoint truncated");
+  if (h.parity != 0 && h.parity != 1) return fail(LBM_EINVAL, "corrupt checkpoint parity");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpyAsync(s.base, static_cast<const char *>(host) + sizeof(h), s.lay.total,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  // the physics of the restored run is the checkpoint's
+  const lbm_case keep = s.cs;
+  s.cs = h.cs;
+  std::string why;
+  if (derive(&s.cs, &s.lat, why) != LBM_OK) {
+    s.cs = keep;
+    (void)derive(&s.cs, &s.lat, why);
+    return fail(LBM_EINVAL, "checkpoint case invalid: " + why);
+  }
+  s.dev = make_dev(&s.cs, s.lat, s.lay, s.base);
+  s.dev.parity = h.parity;
+  s.step = h.step;
+  s.series_step.clear();
+  s.series_parity.clear();
+  drop_graphs(s);
+  c->batch.dirty = true;
+  return LBM_OK;
+}

@@ -210,3 +210,29 @@ def test_budget_admission(P):
         assert ei.value.code == P.LBM_ENOMEM
         c.release(a)
         c.add(case)
+
+
+@pytest.mark.parametrize("pattern,prec", [(0, 0), (1, 0), (0, 1)])
+def test_checkpoint_resume_is_bitwise(P, pattern, prec):
+    case = dict(small_cavity("distinct"), pattern=pattern, precision=prec)
+    print(f"case checkpoint pattern={pattern} precision={prec}", flush=True)
+    with P.Context(device=0, max_slots=2) as ctx:
+        a = ctx.add(case)
+        ctx.step(a, 437)  # odd: the in-place pattern is in its swapped parity
+        blob = ctx.checkpoint(a)
+        ctx.step(a, 563)
+        want, want_st = ctx.state_save(a), ctx.reduce(a)
+    with P.Context(device=0, max_slots=2) as ctx:
+        b = ctx.add(dict(case, Ra=3e4))  # restored slot takes the checkpoint's case
+        ctx.restore(b, blob)
+        assert ctx.info(b)[0] == 437
+        ctx.step(b, 563)
+        got, got_st = ctx.state_save(b), ctx.reduce(b)
+        wrong = ctx.add(dict(case, nx=64))
+        with pytest.raises(P.LbmError):
+            ctx.restore(wrong, blob)
+        with pytest.raises(P.LbmError):
+            ctx.restore(b, blob[:100])
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    for k in ("step", "melt_fraction", "total_H", "heat_in_cum", "budget_residual", "nusselt"):
+        assert got_st[k] == want_st[k], k
