@@ -129,6 +129,28 @@ def fp32_variant(P, steps):
                 melt_fraction=st["melt_fraction"])
 
 
+def hbm_bound_variant(P, steps=200):
+    """The same cavity physics on a 4096x2048 lattice, whose working set (1.2 GB
+    FP64, 604 MB FP32) is far above the 256 MB Infinity Cache: the plainly
+    HBM-bound regime of the step kernel."""
+    from btrirt_workloads import large_cavity
+    out = {}
+    for prec, name in ((0, "fp64"), (1, "fp32s")):
+        case = dict(large_cavity(4096, 2048), precision=prec)
+        ctx = P.Context(device=0, max_slots=1)
+        slot = ctx.add(case)
+        ctx.step(slot, 10)
+        ms = time_steps(P, ctx, slot, steps)
+        ctx.close()
+        cells = 4096 * 2048
+        us = ms * 1e3 / steps
+        gbs = BYTES_PER_LU[prec] * cells / (us * 1e-6) / 1e9
+        out[name] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1), achieved_gbs=round(gbs, 1),
+                         frac=round(gbs / HBM_PEAK_GBS, 4))
+    log(f"hbm-bound 4096x2048: {out}")
+    return out
+
+
 def batched_variant(P, steps, chunk=100):
     """64 cavities of uneven size (seeded sweep), FP32 shifted: one batched
     launch per step replayed from captured 100-step graphs, against the same
@@ -268,6 +290,7 @@ def main():
     }
     if not args.no_extras:
         out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4))
+        out["hbm_bound_4096x2048"] = hbm_bound_variant(P)
         out["batched"] = batched_variant(P, 2000)
         try:
             from paper_1909_13086_amd import serve
