@@ -212,6 +212,40 @@ def cpu_baseline(target_s):
                        f"({el:.1f} s, OpenMP over rows)")
 
 
+def heater_study(P, fo_end, precision, every_fo=0.005):
+    """Heater-position study of Sec. 3.2 (the liquid-fraction curves of Fig. 3b):
+    square 512x512 cavity, Ra = 1e8, Pr = 6.2, Ste = 0.125, heater width
+    D = 0.5 L at centres C = 0.25, 0.375, 0.5 L, all three advanced together in
+    batched launches; melt fraction and Nusselt number every `every_fo` in
+    Fourier number up to `fo_end`."""
+    from btrirt_workloads import cavity
+    cs = [0.25, 0.375, 0.5]
+    cases = [dict(cavity(512, 512, Ra=1e8, Pr=6.2, Ste=0.125, heater_center=c, heater_width=0.5),
+                  precision=precision) for c in cs]
+    lat = P.lbm_derive(P.make_case(cases[0]))
+    steps_per = max(1, int(round(every_fo * 512 * 512 / lat.alpha)))
+    n_rep = int(round(fo_end / every_fo))
+    ctx = P.Context(device=0, max_slots=3)
+    ctx.set_graph_chunk(100)
+    slots = [ctx.add(c) for c in cases]
+    rows = []
+    t0 = time.perf_counter()
+    for k in range(n_rep):
+        ctx.step_many(slots, [steps_per] * 3)
+        st = [ctx.reduce(s, allow_unstable=True) for s in slots]
+        rows.append(dict(fo=round(st[0]["fourier"], 5), step=st[0]["step"],
+                         melt_fraction=[x["melt_fraction"] for x in st], nusselt=[x["nusselt"] for x in st],
+                         finite=[x["finite"] for x in st]))
+        log(f"study Fo={st[0]['fourier']:.4f} step={st[0]['step']} phi={[round(x['melt_fraction'], 5) for x in st]} "
+            f"Nu={[round(x['nusselt'], 2) for x in st]} finite={[x['finite'] for x in st]} "
+            f"({time.perf_counter() - t0:.0f} s)")
+        if not all(x["finite"] for x in st):
+            break
+    ctx.close()
+    return dict(study="heater position", centres=cs, alpha=lat.alpha, steps_per_report=steps_per,
+                precision="fp64" if precision == 0 else "fp32s", series=rows)
+
+
 def calib_copy(nbytes):
     """Plain device copy of a known size, for scaling HBM counters."""
     import torch
@@ -236,6 +270,10 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
     ap.add_argument("--only", choices=["fp32", "batched", "serving"], default="",
                     help="run one variant alone (for profiling) and print its result")
+    ap.add_argument("--study", choices=["heater"], default="",
+                    help="run the heater-position study of the cavity section instead of the benchmark")
+    ap.add_argument("--fo", type=float, default=0.1, help="study: final Fourier number")
+    ap.add_argument("--precision", choices=["fp64", "fp32s"], default="fp64", help="study precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -245,6 +283,11 @@ def main():
         calib_copy(args.calib_copy)
         return
     import paper_1909_13086_amd as P
+
+    if args.study:
+        res = heater_study(P, args.fo, 0 if args.precision == "fp64" else 1)
+        print(json.dumps(res), flush=True)
+        return
 
     if args.only:
         if args.only == "fp32":
