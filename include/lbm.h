@@ -201,7 +201,8 @@ int lbm_checkpoint_load(lbm_ctx *c, int slot, const void *host, size_t n);
 
 enum {
   LBM_LAUNCH_XCD_BANDS = 1,  /* each of the 8 XCDs gets a contiguous band of tiles */
-  LBM_LAUNCH_NONTEMPORAL = 2 /* population loads/stores bypass cache retention */
+  LBM_LAUNCH_NONTEMPORAL = 2, /* population loads/stores bypass cache retention */
+  LBM_LAUNCH_ALTERNATE = 4   /* tiles walked backwards on every other step */
 };
 /* Tile of the single-cavity step kernels for a precision: bx threads along x
  * (multiple of 64), by rows per block (bx*by <= 256), cpl rows per lane (1, 2

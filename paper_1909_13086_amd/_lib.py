@@ -22,7 +22,7 @@ LBM_INIT_SOLID_AT_TM, LBM_INIT_LIQUID_T0, LBM_INIT_GAUSSIAN = 0, 1, 2
 LBM_FIELD_T, LBM_FIELD_FL, LBM_FIELD_H, LBM_FIELD_UX, LBM_FIELD_UY, LBM_FIELD_RHO = 1, 2, 4, 8, 16, 32
 FIELD_NAMES = ("T", "fl", "H", "ux", "uy", "rho")
 LBM_ALL = -1
-LBM_LAUNCH_XCD_BANDS, LBM_LAUNCH_NONTEMPORAL = 1, 2
+LBM_LAUNCH_XCD_BANDS, LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_ALTERNATE = 1, 2, 4
 
 # Names exported by include/lbm.h and include/lbm_serve.h.
 EXPORTS = (

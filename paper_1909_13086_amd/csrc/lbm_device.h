@@ -361,5 +361,17 @@ __device__ __forceinline__ int xcd_band(int b, int nb) {
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// Tile handled by workgroup b of nb: XCD bands or plain order, optionally
+// walked backwards.  Alternating the walk direction between steps makes a step
+// start where the previous one ended, on the lines the last-level cache holds.
+__device__ __forceinline__ int tile_of(int b, int nb, bool bands, bool backwards) {
+  if (!bands) return backwards ? nb - 1 - b : b;
+  const int xcd = b % kXcds, local = b / kXcds;
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int count = q + (xcd < r ? 1 : 0);
+  const int start = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+  return start + (backwards ? count - 1 - local : local);
+}
+
 }  // namespace dev
 }  // namespace lbm

@@ -948,6 +948,7 @@ int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags
   L.cpl = cpl;
   L.xcd = (flags & LBM_LAUNCH_XCD_BANDS) ? 1 : 0;
   L.nt = (flags & LBM_LAUNCH_NONTEMPORAL) ? 1 : 0;
+  L.reverse = (flags & LBM_LAUNCH_ALTERNATE) ? 1 : 0;
   for (auto &s : c->slots) drop_graphs(s);
   return LBM_OK;
 }
@@ -959,7 +960,8 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
   *bx = L.bx;
   *by = L.by;
   *cpl = L.cpl;
-  *flags = (L.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (L.nt ? LBM_LAUNCH_NONTEMPORAL : 0);
+  *flags = (L.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (L.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
+           (L.reverse ? LBM_LAUNCH_ALTERNATE : 0);
   return LBM_OK;
 }
 
@@ -1100,13 +1102,14 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   const int reps = 10;
   for (const auto &sh : shapes) {
     for (int cpl : cpls) {
-      for (int flags = 0; flags < 4 && rc == LBM_OK; ++flags) {
+      for (int flags = 0; flags < 8 && rc == LBM_OK; ++flags) {
         LaunchCfg cfg;
         cfg.bx = sh[0];
         cfg.by = sh[1];
         cfg.cpl = cpl;
         cfg.xcd = flags & LBM_LAUNCH_XCD_BANDS ? 1 : 0;
         cfg.nt = flags & LBM_LAUNCH_NONTEMPORAL ? 1 : 0;
+        cfg.reverse = flags & LBM_LAUNCH_ALTERNATE ? 1 : 0;
         hipError_t e = hipSuccess;
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
           e = lbm::launch_step(d, precision, cfg, c->stream);
@@ -1140,8 +1143,9 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
     c->launch[precision] = saved;
     return rc;
   }
-  const int best_flags =
-      (best.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (best.nt ? LBM_LAUNCH_NONTEMPORAL : 0);
+  const int best_flags = (best.xcd ? LBM_LAUNCH_XCD_BANDS : 0) |
+                         (best.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
+                         (best.reverse ? LBM_LAUNCH_ALTERNATE : 0);
   cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best_flags,
                 1000.0 * best_ms / reps};
   write_cache(cache_path, cache);

@@ -8,11 +8,12 @@ namespace {
 using namespace dev;
 
 // Tile of bx x (by*CPL) cells per workgroup; each lane updates CPL cells of
-// one column.  With xcd set, consecutive tiles go to one XCD (contiguous bands
-// per XCD share its L2 at tile edges).
+// one column.  order bit 0: consecutive tiles go to one XCD (contiguous bands
+// per XCD share its L2 at tile edges); bit 1: walk the tiles backwards on odd
+// storage parity.
 template <typename S, typename R, int CPL, bool NT>
-__global__ __launch_bounds__(256) void k_step(CavDev c, int tiles_x, int xcd) {
-  const int b = xcd ? xcd_band(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+__global__ __launch_bounds__(256) void k_step(CavDev c, int tiles_x, int order) {
+  const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
   const int tx = b % tiles_x, ty = b / tiles_x;
   const int x = tx * blockDim.x + threadIdx.x;
   const int ybase = ty * blockDim.y * CPL + threadIdx.y;
@@ -33,10 +34,11 @@ hipError_t dispatch_cpl(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int tiles_y = (c.ny + rows - 1) / rows;
   const dim3 block(cfg.bx, cfg.by);
   const dim3 grid(tiles_x * tiles_y);
+  const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0);
   switch (cfg.cpl) {
-    case 1: hipLaunchKernelGGL((k_step<S, R, 1, NT>), grid, block, 0, s, c, tiles_x, cfg.xcd); break;
-    case 2: hipLaunchKernelGGL((k_step<S, R, 2, NT>), grid, block, 0, s, c, tiles_x, cfg.xcd); break;
-    case 4: hipLaunchKernelGGL((k_step<S, R, 4, NT>), grid, block, 0, s, c, tiles_x, cfg.xcd); break;
+    case 1: hipLaunchKernelGGL((k_step<S, R, 1, NT>), grid, block, 0, s, c, tiles_x, order); break;
+    case 2: hipLaunchKernelGGL((k_step<S, R, 2, NT>), grid, block, 0, s, c, tiles_x, order); break;
+    case 4: hipLaunchKernelGGL((k_step<S, R, 4, NT>), grid, block, 0, s, c, tiles_x, order); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -139,8 +139,10 @@ def test_patterns_and_tiles_agree_bitwise(ctx, P, steps):
     base = small_cavity("distinct")
     f0, g0 = _random_state(9, 128, 64)
     ref = _run_state(ctx, P, dict(base, pattern=P.LBM_PATTERN_AB), steps, f0, g0)
-    # (bx, by, cpl, flags): flags bit 0 = XCD bands, bit 1 = non-temporal access
-    for launch in [(256, 1, 1, 1), (64, 4, 2, 0), (128, 2, 4, 1), (64, 1, 1, 0), (256, 1, 1, 3), (128, 2, 2, 2)]:
+    # (bx, by, cpl, flags): flags bit 0 = XCD bands, bit 1 = non-temporal access,
+    # bit 2 = tiles walked backwards on every other step
+    for launch in [(256, 1, 1, 1), (64, 4, 2, 0), (128, 2, 4, 1), (64, 1, 1, 0), (256, 1, 1, 3), (128, 2, 2, 2),
+                   (64, 1, 1, 5), (128, 2, 2, 4), (64, 4, 1, 7)]:
         got = _run_state(ctx, P, dict(base), steps, f0, g0, launch)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), launch
     ctx.set_launch(0, 256, 1, 1, 1)
