@@ -206,7 +206,8 @@ enum {
 };
 /* Tile of the single-cavity step kernels for a precision: bx threads along x
  * (multiple of 64), by rows per block (bx*by <= 256), cpl rows per lane (1, 2
- * or 4) and LBM_LAUNCH_* flags.  Default 256, 1, 1, LBM_LAUNCH_XCD_BANDS.
+ * or 4) and LBM_LAUNCH_* flags.  Default 256, 1, 1,
+ * LBM_LAUNCH_XCD_BANDS | LBM_LAUNCH_ALTERNATE.
  * Results do not depend on the tile or the flags. */
 int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags);
 int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags);

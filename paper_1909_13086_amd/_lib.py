@@ -290,7 +290,7 @@ def lbm_checkpoint_load(ctx, slot, blob):
 
 # ---- execution control --------------------------------------------------------
 
-def lbm_set_launch(ctx, precision, bx, by, cpl, flags=LBM_LAUNCH_XCD_BANDS):
+def lbm_set_launch(ctx, precision, bx, by, cpl, flags=LBM_LAUNCH_XCD_BANDS | LBM_LAUNCH_ALTERNATE):
     _check(lib().lbm_set_launch(ctx, int(precision), int(bx), int(by), int(cpl), int(flags)))
 
 

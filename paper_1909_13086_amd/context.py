@@ -98,7 +98,7 @@ class Context:
     def series(self, slot):
         return L.lbm_series(self.h, slot)
 
-    def set_launch(self, precision, bx, by, cpl, flags=L.LBM_LAUNCH_XCD_BANDS):
+    def set_launch(self, precision, bx, by, cpl, flags=L.LBM_LAUNCH_XCD_BANDS | L.LBM_LAUNCH_ALTERNATE):
         L.lbm_set_launch(self.h, precision, bx, by, cpl, flags)
 
     def set_graph_chunk(self, chunk):

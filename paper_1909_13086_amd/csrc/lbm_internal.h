@@ -48,7 +48,7 @@ struct LaunchCfg {
   int bx = 256, by = 1, cpl = 1;
   int xcd = 1;  // contiguous tile bands per XCD
   int nt = 0;   // non-temporal population loads and stores
-  int reverse = 0;  // walk tiles backwards on odd storage parity
+  int reverse = 1;  // walk tiles backwards on odd storage parity
 };
 
 // Accumulators of one reduction, FP64.

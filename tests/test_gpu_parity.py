@@ -145,7 +145,7 @@ def test_patterns_and_tiles_agree_bitwise(ctx, P, steps):
                    (64, 1, 1, 5), (128, 2, 2, 4), (64, 4, 1, 7)]:
         got = _run_state(ctx, P, dict(base), steps, f0, g0, launch)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), launch
-    ctx.set_launch(0, 256, 1, 1, 1)
+    ctx.set_launch(0, 256, 1, 1, 5)
 
 
 def test_graph_chunks_equal_plain_launches(ctx, P):
