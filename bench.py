@@ -276,7 +276,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32s"], default="fp64", help="study precision")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}), flush=True)
         sys.exit(2)
     if args.calib_copy:
