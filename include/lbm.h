@@ -211,6 +211,13 @@ enum {
  * Results do not depend on the tile or the flags. */
 int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags);
 int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags);
+/* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2 a
+ * single launch advances a LBM_PATTERN_AB slot by two steps, reading its
+ * lattice once and writing the other once (each wavefront walks a strip of
+ * 62 columns up a segment of segment_rows rows, 8, 16 or 32, keeping a
+ * three-row window of first-step values in registers).  Results equal those
+ * of single steps bit for bit.  Default 1 (off). */
+int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
 int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
 /* Times the candidate tiles on a scratch cavity of the given size and

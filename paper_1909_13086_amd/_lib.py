@@ -31,7 +31,7 @@ EXPORTS = (
     "lbm_fields", "lbm_set_report", "lbm_series", "lbm_state_load", "lbm_state_save",
     "lbm_set_launch", "lbm_get_launch", "lbm_set_graph_chunk", "lbm_autotune", "lbm_sync",
     "lbm_stream", "lbm_slot_info", "lbm_step_many", "lbm_set_group_bytes",
-    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load",
+    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_set_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
     "lbm_server_request", "lbm_server_summary",
 )
@@ -142,6 +142,7 @@ def lib():
                                               ctypes.c_int]),
             "lbm_get_launch": (ctypes.c_int, [vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4),
             "lbm_set_graph_chunk": (ctypes.c_int, [vp, ctypes.c_int]),
+            "lbm_set_fusion": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "lbm_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p]),
             "lbm_sync": (ctypes.c_int, [vp]),
             "lbm_checkpoint_bytes": (ctypes.c_size_t, [vp, ctypes.c_int]),
@@ -298,6 +299,10 @@ def lbm_get_launch(ctx, precision):
     v = [ctypes.c_int() for _ in range(4)]
     _check(lib().lbm_get_launch(ctx, int(precision), *(ctypes.byref(x) for x in v)))
     return tuple(x.value for x in v)
+
+
+def lbm_set_fusion(ctx, precision, steps_per_launch, segment_rows=16):
+    _check(lib().lbm_set_fusion(ctx, int(precision), int(steps_per_launch), int(segment_rows)))
 
 
 def lbm_set_graph_chunk(ctx, chunk):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_step.hip", "lbm_batch.hip", "lbm_aux.hip", "lbm_runtime.hip", "lbm_serve.hip"]
+SOURCES = ["lbm_step.hip", "lbm_step2.hip", "lbm_batch.hip", "lbm_aux.hip", "lbm_runtime.hip", "lbm_serve.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -101,6 +101,9 @@ class Context:
     def set_launch(self, precision, bx, by, cpl, flags=L.LBM_LAUNCH_XCD_BANDS | L.LBM_LAUNCH_ALTERNATE):
         L.lbm_set_launch(self.h, precision, bx, by, cpl, flags)
 
+    def set_fusion(self, precision, steps_per_launch, segment_rows=16):
+        L.lbm_set_fusion(self.h, precision, steps_per_launch, segment_rows)
+
     def set_graph_chunk(self, chunk):
         L.lbm_set_graph_chunk(self.h, chunk)
 

@@ -49,6 +49,8 @@ struct LaunchCfg {
   int xcd = 1;  // contiguous tile bands per XCD
   int nt = 0;   // non-temporal population loads and stores
   int reverse = 1;  // walk tiles backwards on odd storage parity
+  int fuse = 1;     // steps per launch of the two-lattice pattern (1 or 2)
+  int seg = 16;     // rows per wavefront segment of the two-step kernel
 };
 
 // Accumulators of one reduction, FP64.
@@ -70,6 +72,9 @@ constexpr int kRedThreads = 256;
 hipError_t launch_init(const CavDev &c, int precision, int mode, double T0, double amp,
                        double sigma, hipStream_t s);
 hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
+// Two steps of the two-lattice pattern in one launch: reads pop[parity],
+// writes pop[parity ^ 1].
+hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
 // entries (the kernel ignores a header that points outside them).
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,

@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -176,6 +178,7 @@ struct Slot {
   std::vector<int32_t> series_parity;
   // captured step chunks, keyed by starting parity
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_after[2] = {0, 1};  // storage parity after a replay
   int graph_chunk = 0;
 };
 
@@ -351,6 +354,38 @@ int enqueue_one_step(lbm_ctx *c, Slot &s) {
   return LBM_OK;
 }
 
+// Two-lattice slots may advance two steps per launch.
+bool fused(const lbm_ctx *c, const Slot &s) {
+  return s.cs.pattern == LBM_PATTERN_AB && c->launch[s.cs.precision].fuse == 2;
+}
+
+int enqueue_two_steps(lbm_ctx *c, Slot &s) {
+  HIP_TRY(lbm::launch_step2(s.dev, s.cs.precision, c->launch[s.cs.precision], c->stream));
+  s.dev.parity ^= 1;  // the state moved to the other lattice
+  s.step += 2;
+  return LBM_OK;
+}
+
+// Launches of a chunk of n steps starting from parity p: the fused kernel
+// takes pairs, a single step finishes an odd count.  Returns the storage
+// parity after the chunk.
+int enqueue_chunk(lbm_ctx *c, const Slot &s, CavDev d, int n, hipError_t *err) {
+  const LaunchCfg &L = c->launch[s.cs.precision];
+  *err = hipSuccess;
+  int k = 0;
+  if (fused(c, s)) {
+    for (; k + 2 <= n && *err == hipSuccess; k += 2) {
+      *err = lbm::launch_step2(d, s.cs.precision, L, c->stream);
+      d.parity ^= 1;
+    }
+  }
+  for (; k < n && *err == hipSuccess; ++k) {
+    *err = lbm::launch_step(d, s.cs.precision, L, c->stream);
+    d.parity ^= 1;
+  }
+  return d.parity;
+}
+
 int record_report(lbm_ctx *c, Slot &s) {
   if (s.report_every <= 0 || s.step % s.report_every != 0) return LBM_OK;
   const int32_t k = (int32_t)s.series_step.size();
@@ -361,17 +396,14 @@ int record_report(lbm_ctx *c, Slot &s) {
   return LBM_OK;
 }
 
-// Captures `chunk` steps (chunk even) starting at storage parity p.
+// Captures a chunk of steps starting at storage parity p.
 int capture_chunk(lbm_ctx *c, Slot &s, int p, int chunk) {
   CavDev d = s.dev;
   d.parity = p;
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
-  for (int k = 0; k < chunk && err == hipSuccess; ++k) {
-    err = lbm::launch_step(d, s.cs.precision, c->launch[s.cs.precision], c->stream);
-    d.parity ^= 1;
-  }
+  const int after = enqueue_chunk(c, s, d, chunk, &err);
   hipError_t e2 = hipStreamEndCapture(c->stream, &g);
   if (err != hipSuccess || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -383,6 +415,7 @@ int capture_chunk(lbm_ctx *c, Slot &s, int p, int chunk) {
   (void)hipGraphDestroy(g);
   if (e3 != hipSuccess) return fail(LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e3));
   s.graph[p] = ex;
+  s.graph_after[p] = after;
   return LBM_OK;
 }
 
@@ -393,29 +426,32 @@ int step_slot(lbm_ctx *c, Slot &s, int64_t n) {
     s.graph_chunk = chunk;
   }
   while (n > 0) {
-    // graph replay only when no report falls inside the chunk
+    // graph replay only when no report falls strictly inside the chunk
     bool use_graph = chunk > 0 && n >= chunk;
-    if (use_graph && s.report_every > 0) {
-      const int64_t next = (s.step / s.report_every + 1) * s.report_every;
-      if (next <= s.step + chunk) use_graph = false;
-    }
+    const int64_t next =
+        s.report_every > 0 ? (s.step / s.report_every + 1) * s.report_every : INT64_MAX;
+    if (use_graph && next < s.step + chunk) use_graph = false;
+    int rc = LBM_OK;
     if (use_graph) {
       const int p = s.dev.parity;
       if (!s.graph[p]) {
-        int rc = capture_chunk(c, s, p, chunk);
+        rc = capture_chunk(c, s, p, chunk);
         if (rc != LBM_OK) return rc;
       }
       HIP_TRY(hipGraphLaunch(s.graph[p], c->stream));
       s.step += chunk;
-      if (chunk & 1) s.dev.parity ^= 1;
+      s.dev.parity = s.graph_after[p];
       n -= chunk;
-      continue;
+    } else if (fused(c, s) && n >= 2 && next != s.step + 1) {
+      rc = enqueue_two_steps(c, s);
+      n -= 2;
+    } else {
+      rc = enqueue_one_step(c, s);
+      n -= 1;
     }
-    int rc = enqueue_one_step(c, s);
     if (rc != LBM_OK) return rc;
     rc = record_report(c, s);
     if (rc != LBM_OK) return rc;
-    n -= 1;
   }
   return LBM_OK;
 }
@@ -962,6 +998,18 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
   *cpl = L.cpl;
   *flags = (L.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (L.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
            (L.reverse ? LBM_LAUNCH_ALTERNATE : 0);
+  return LBM_OK;
+}
+
+int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
+  if ((steps_per_launch != 1 && steps_per_launch != 2) ||
+      (segment_rows != 8 && segment_rows != 16 && segment_rows != 32))
+    return fail(LBM_EINVAL, "steps per launch in {1, 2}, segment rows in {8, 16, 32}");
+  c->launch[precision].fuse = steps_per_launch;
+  c->launch[precision].seg = segment_rows;
+  for (auto &s : c->slots) drop_graphs(s);
   return LBM_OK;
 }
 

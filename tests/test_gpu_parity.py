@@ -238,3 +238,65 @@ def test_checkpoint_resume_is_bitwise(P, pattern, prec):
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
     for k in ("step", "melt_fraction", "total_H", "heat_in_cum", "budget_residual", "nusselt"):
         assert got_st[k] == want_st[k], k
+
+
+FUSED_GEOMS = GEOMS + [(130, 70, 0, 0, 0.4, 0.3), (200, 37, 1, 1, 0.5, 0.25), (63, 17, 1, 0, 0.6, 0.5)]
+
+
+@pytest.mark.parametrize("geom", FUSED_GEOMS, ids=[f"{g[0]}x{g[1]}p{g[2]}{g[3]}" for g in FUSED_GEOMS])
+@pytest.mark.parametrize("prec,seg,steps", [(0, 8, 2), (0, 16, 7), (1, 32, 6), (0, 32, 13), (1, 8, 5)])
+def test_two_step_kernel_equals_single_steps(P, geom, prec, seg, steps):
+    nx, ny, px, py, hc, hw = geom
+    case = dict(cavity(nx, ny, periodic_x=px, periodic_y=py, heater_center=hc, heater_width=hw,
+                       param_mode=1, nu=0.04, alpha=0.06, gbeta=3e-3, latent=0.8, Tm=0.1, Th=0.9,
+                       k0_g=0.9, k2_g=1.2, k0_f=1.1, k1_f=0.85),
+                precision=prec, pattern=P.LBM_PATTERN_AB)
+    print(f"case two-step {nx}x{ny} periodic=({px},{py}) prec={prec} seg={seg} steps={steps}", flush=True)
+    f0, g0 = _random_state(2000 + nx + ny, nx, ny)
+    out = []
+    for fuse in (1, 2):
+        with P.Context(device=0, max_slots=1) as ctx:
+            ctx.set_fusion(prec, fuse, seg)
+            s = ctx.add(case)
+            ctx.state_load(s, f0, g0)
+            ctx.step(s, steps)
+            out.append((ctx.state_save(s), ctx.reduce(s)))
+    (a, sa), (b, sb) = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for k in ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "budget_residual"):
+        assert sa[k] == sb[k], k
+
+
+@pytest.mark.parametrize("chunk", [7, 10])
+def test_two_step_kernel_in_graphs_and_with_reports(P, chunk):
+    case = dict(small_cavity("distinct"), pattern=P.LBM_PATTERN_AB)
+    f0, g0 = _random_state(31, 128, 64)
+    res = []
+    for fuse in (1, 2):
+        with P.Context(device=0, max_slots=1) as ctx:
+            ctx.set_fusion(0, fuse, 16)
+            ctx.set_graph_chunk(chunk)
+            s = ctx.add(case)
+            ctx.state_load(s, f0, g0)
+            ctx.set_report(s, 5, 64)
+            ctx.step(s, 53)
+            res.append((ctx.state_save(s), ctx.series(s)))
+    (a, sa), (b, sb) = res
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert [e["step"] for e in sa] == [e["step"] for e in sb] == list(range(5, 53, 5))
+    assert all(x["total_H"] == y["total_H"] for x, y in zip(sa, sb))
+
+
+def test_two_step_kernel_full_size_matches_oracle(P):
+    case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB)
+    print("case 2048x1024 FP64 two-step kernel, 6 steps vs oracle", flush=True)
+    f0, g0 = _random_state(23, 2048, 1024)
+    with P.Context(device=0, max_slots=1) as ctx:
+        ctx.set_fusion(0, 2, 16)
+        s = ctx.add(case)
+        ctx.state_load(s, f0, g0)
+        ctx.step(s, 6)
+        got = ctx.fields(s)
+    o = oracle_run(case, 6, f0, g0)
+    err = max_field_err(got, o.fields())
+    assert max(err.values()) <= 1e-12, err
