@@ -214,7 +214,7 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
 /* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2 a
  * single launch advances a LBM_PATTERN_AB slot by two steps, reading its
  * lattice once and writing the other once (each wavefront walks a strip of
- * 62 columns up a segment of segment_rows rows, 8, 16 or 32, keeping a
+ * 62 columns up a segment of segment_rows rows, 4, 8, 16 or 32, keeping a
  * three-row window of first-step values in registers).  Results equal those
  * of single steps bit for bit.  Default 1 (off). */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);

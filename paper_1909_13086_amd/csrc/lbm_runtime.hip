@@ -1005,8 +1005,8 @@ int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
   if ((steps_per_launch != 1 && steps_per_launch != 2) ||
-      (segment_rows != 8 && segment_rows != 16 && segment_rows != 32))
-    return fail(LBM_EINVAL, "steps per launch in {1, 2}, segment rows in {8, 16, 32}");
+      (segment_rows != 4 && segment_rows != 8 && segment_rows != 16 && segment_rows != 32))
+    return fail(LBM_EINVAL, "steps per launch in {1, 2}, segment rows in {4, 8, 16, 32}");
   c->launch[precision].fuse = steps_per_launch;
   c->launch[precision].seg = segment_rows;
   for (auto &s : c->slots) drop_graphs(s);

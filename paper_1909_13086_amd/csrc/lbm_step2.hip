@@ -151,6 +151,7 @@ hipError_t dispatch_seg(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 template <typename S, typename R>
 hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   switch (cfg.seg) {
+    case 4: return dispatch_seg<S, R, 4>(c, cfg, s);
     case 8: return dispatch_seg<S, R, 8>(c, cfg, s);
     case 16: return dispatch_seg<S, R, 16>(c, cfg, s);
     case 32: return dispatch_seg<S, R, 32>(c, cfg, s);
