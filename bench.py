@@ -151,6 +151,29 @@ def hbm_bound_variant(P, steps=200):
     return out
 
 
+def two_step_variant(P, steps=400):
+    """The same cavity on the two-lattice pattern with the two-step
+    (temporally blocked) kernel: each launch reads one lattice once and writes
+    the other once for two time steps."""
+    from btrirt_workloads import large_cavity
+    out = {}
+    for nx, ny in ((2048, 1024), (4096, 2048)):
+        case = dict(large_cavity(nx, ny), pattern=P.LBM_PATTERN_AB)
+        ctx = P.Context(device=0, max_slots=1)
+        slot = ctx.add(case)
+        ctx.step(slot, 10)
+        ms = time_steps(P, ctx, slot, steps)
+        ctx.close()
+        us = ms * 1e3 / steps
+        cells = nx * ny
+        gbs = 2 * BYTES_PER_LU[0] * cells / (2 * us * 1e-6) / 1e9
+        out[f"{nx}x{ny}"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
+                                 us_per_launch=round(2 * us, 2),
+                                 achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    log(f"two-step two-lattice FP64: {out}")
+    return out
+
+
 def batched_variant(P, steps, chunk=100):
     """64 cavities of uneven size (seeded sweep), FP32 shifted: one batched
     launch per step replayed from captured 100-step graphs, against the same
@@ -268,7 +291,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
-    ap.add_argument("--only", choices=["fp32", "batched", "serving"], default="",
+    ap.add_argument("--only", choices=["fp32", "batched", "serving", "two_step"], default="",
                     help="run one variant alone (for profiling) and print its result")
     ap.add_argument("--study", choices=["heater"], default="",
                     help="run the heater-position study of the cavity section instead of the benchmark")
@@ -294,6 +317,8 @@ def main():
             res = fp32_variant(P, max(500, args.steps // 4))
         elif args.only == "batched":
             res = batched_variant(P, args.steps)
+        elif args.only == "two_step":
+            res = two_step_variant(P, args.steps)
         else:
             from paper_1909_13086_amd import serve
             res = serve.bench_serving(P)
@@ -334,6 +359,7 @@ def main():
     if not args.no_extras:
         out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4))
         out["hbm_bound_4096x2048"] = hbm_bound_variant(P)
+        out["two_step_two_lattice_fp64"] = two_step_variant(P)
         out["batched"] = batched_variant(P, 2000)
         try:
             from paper_1909_13086_amd import serve

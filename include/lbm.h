@@ -216,7 +216,7 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * lattice once and writing the other once (each wavefront walks a strip of
  * 62 columns up a segment of segment_rows rows, 4, 8, 16 or 32, keeping a
  * three-row window of first-step values in registers).  Results equal those
- * of single steps bit for bit.  Default 1 (off). */
+ * of single steps bit for bit.  Default 2 steps per launch, 4-row segments. */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
 int lbm_set_graph_chunk(lbm_ctx *c, int chunk);

@@ -49,8 +49,8 @@ struct LaunchCfg {
   int xcd = 1;  // contiguous tile bands per XCD
   int nt = 0;   // non-temporal population loads and stores
   int reverse = 1;  // walk tiles backwards on odd storage parity
-  int fuse = 1;     // steps per launch of the two-lattice pattern (1 or 2)
-  int seg = 16;     // rows per wavefront segment of the two-step kernel
+  int fuse = 2;     // steps per launch of the two-lattice pattern (1 or 2)
+  int seg = 4;      // rows per wavefront segment of the two-step kernel
 };
 
 // Accumulators of one reduction, FP64.
