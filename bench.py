@@ -3,15 +3,16 @@
 Workload (the single-GPU configuration the metric is quoted on): one
 2048x1024 D2Q9 cavity, FP64, Ra = 1e8, Pr = 1, Ste = 1, heater centred with
 width W/4, starting all solid at Tm; flow and enthalpy populations advanced by
-the in-place fused collide-and-stream kernel, diagnostics (melt fraction,
-Nusselt number, enthalpy budget) reduced on the device every 100 steps.  A
-"step" is one time step of that whole path.  Inputs are synthetic and
-resident in HBM before timing starts.
+the fused collide-and-stream kernel on two lattices, two time steps per launch
+(--path aa: the in-place kernel, one step per launch), diagnostics (melt
+fraction, Nusselt number, enthalpy budget) reduced on the device every 100
+steps.  A "step" is one time step of that whole path.  Inputs are synthetic
+and resident in HBM before timing starts.
 
 Printed: one JSON line with MLUPS (10^6 lattice updates per second, one update
 = one cell's f and g advanced one step), the roofline of the step kernel, the
-oracle timed on the host cores, and the FP32-shifted, batched and served
-variants.
+oracle timed on the host cores, and the in-place, FP32-shifted, 4096x2048,
+batched and served variants.
 """
 import argparse
 import hashlib
@@ -27,34 +28,44 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_LU = {0: 288, 1: 144}  # 18 populations read + written, FP64 / FP32
 REPORT_EVERY = 100
-# sources of the step kernel: a change to either invalidates stored counter traffic
-KERNEL_SRC = [os.path.join(ROOT, "paper_1909_13086_amd", "csrc", f) for f in ("lbm_device.h", "lbm_step.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md")
+# per path: kernel name, sources (a change to any invalidates stored counter
+# traffic), counter summary, steps per launch
+CSRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc")
+PATHS = {
+    "ab2": dict(kernel="k_step2<double,double,4>", src=("lbm_device.h", "lbm_step2.hip"),
+                traffic=os.path.join(ROOT, "profiles", "traffic_k_step2_fp64_2048x1024.md"), per_launch=2,
+                pattern="two lattices, two steps per launch"),
+    "aa": dict(kernel="k_step<double,double,1>", src=("lbm_device.h", "lbm_step.hip"),
+               traffic=os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md"), per_launch=1,
+               pattern="in-place A-A, one step per launch"),
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def kernel_hash(path):
     h = hashlib.sha256()
-    for path in KERNEL_SRC:
-        with open(path, "rb") as fh:
+    for f in PATHS[path]["src"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, or None when absent or taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path):
+    """HBM bytes per launch of the path's step kernel from the committed
+    rocprofv3 counter summary, or None when absent or taken on a different
+    kernel source."""
+    fn = PATHS[path]["traffic"]
+    if not os.path.exists(fn):
         return None
     vals = {}
-    for ln in open(TRAFFIC_FILE):
+    for ln in open(fn):
         if ":" in ln:
             k, v = ln.split(":", 1)
             vals[k.strip().strip("-* `")] = v.strip().strip("` ")
-    if vals.get("kernel_source_sha256") != kernel_hash():
+    if vals.get("kernel_source_sha256") != kernel_hash(path):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -76,45 +87,66 @@ def time_steps(P, ctx, slot, steps, events=True):
     return e0.elapsed_time(e1)
 
 
-def main_workload(P, args):
+def run_cavity(P, path, steps, warmup, report_every=REPORT_EVERY, graph_chunk=0, tile=""):
+    """The 2048x1024 FP64 cavity on a path ("ab2" or "aa"): `warmup` steps,
+    then `steps` timed steps with diagnostics every `report_every`, then a
+    kernel-only timing of whole launches."""
     from btrirt_workloads import large_cavity
     import torch
 
-    case = large_cavity()
+    case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB if path == "ab2" else P.LBM_PATTERN_AA)
     cells = case["nx"] * case["ny"]
     ctx = P.Context(device=0, max_slots=2)
-    if args.graph_chunk:
-        ctx.set_graph_chunk(args.graph_chunk)
-    if args.tile:
-        bx, by, cpl, xcd = (int(v) for v in args.tile.split(","))
-        ctx.set_launch(0, bx, by, cpl, xcd)
+    if graph_chunk:
+        ctx.set_graph_chunk(graph_chunk)
+    if tile:
+        bx, by, cpl, flags = (int(v) for v in tile.split(","))
+        ctx.set_launch(0, bx, by, cpl, flags)
     slot = ctx.add(case)
-    ctx.set_report(slot, REPORT_EVERY, (args.steps + args.warmup) // REPORT_EVERY + 2)
-    log(f"main: 2048x1024 FP64 in place, warmup {args.warmup}, steps {args.steps}")
-    ctx.step(slot, args.warmup)
+    if report_every:
+        ctx.set_report(slot, report_every, (steps + warmup) // report_every + 2)
+    ctx.step(slot, warmup)
     ctx.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms = time_steps(P, ctx, slot, args.steps)
+    ms = time_steps(P, ctx, slot, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.reduce(slot)
-    series = ctx.series(slot)
-    log(f"main: {ms:.1f} ms event, {wall * 1e3:.1f} ms wall, melt fraction {st['melt_fraction']:.6f}, "
-        f"Nu {st['nusselt']:.3f}, finite {st['finite']}, {len(series)} reports")
-    # live kernel time of the step kernel alone (no reports in the region)
+    series = ctx.series(slot) if report_every else []
+    # live time of the step kernel alone (whole launches, no diagnostics)
     slot2 = ctx.add(case)
-    k2 = max(200, min(2000, args.steps))
+    k2 = 2 * max(100, min(1000, steps // 2))
     ctx.step(slot2, 20)
     kms = time_steps(P, ctx, slot2, k2)
     ctx.close()
+    per = PATHS[path]["per_launch"]
     return dict(case=case, cells=cells, ms=ms, wall=wall, stats=st, series=series,
-                kernel_ms=kms / k2, kernel_launches=k2)
+                launch_ms=kms / k2 * per, launches=k2 // per, steps_per_launch=per)
 
 
-def fp32_variant(P, steps):
+def roofline(path, m):
+    alg = BYTES_PER_LU[0] * m["cells"] * m["steps_per_launch"]
+    achieved = alg / (m["launch_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(path),
+            "kernel": PATHS[path]["kernel"], "kernel_avg_us": round(m["launch_ms"] * 1e3, 2),
+            "steps_per_launch": m["steps_per_launch"], "algorithmic_bytes_per_launch": alg}
+
+
+def in_place_variant(P, steps):
+    """The same workload on the in-place A-A pattern (half the memory)."""
+    m = run_cavity(P, "aa", steps, 100)
+    mlups = m["cells"] * steps / (m["ms"] * 1e-3) / 1e6
+    log(f"in-place A-A: {mlups:.0f} MLUPS, {m['launch_ms'] * 1e3:.2f} us/launch")
+    return dict(mlups=round(mlups, 1), ms_per_step=round(m["ms"] / steps, 5), roofline=roofline("aa", m),
+                melt_fraction=m["stats"]["melt_fraction"])
+
+
+def fp32_variant(P, steps, path="ab2"):
     from btrirt_workloads import large_cavity
-    case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED)
+    case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED,
+                pattern=P.LBM_PATTERN_AB if path == "ab2" else P.LBM_PATTERN_AA)
     ctx = P.Context(device=0, max_slots=1)
     slot = ctx.add(case)
     ctx.step(slot, 100)
@@ -123,30 +155,31 @@ def fp32_variant(P, steps):
     ctx.close()
     cells = case["nx"] * case["ny"]
     mlups = cells * steps / (ms * 1e-3) / 1e6
-    log(f"fp32s: {mlups:.0f} MLUPS")
-    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps,
+    log(f"fp32s ({PATHS[path]['pattern']}): {mlups:.0f} MLUPS")
+    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=PATHS[path]["pattern"],
                 hbm_frac=round(mlups * 1e6 * BYTES_PER_LU[1] / (HBM_PEAK_GBS * 1e9), 4),
                 melt_fraction=st["melt_fraction"])
 
 
 def hbm_bound_variant(P, steps=200):
     """The same cavity physics on a 4096x2048 lattice, whose working set (1.2 GB
-    FP64, 604 MB FP32) is far above the 256 MB Infinity Cache: the plainly
-    HBM-bound regime of the step kernel."""
+    FP64 and 604 MB FP32 in place, twice that on two lattices) is far above the
+    256 MB Infinity Cache: the HBM-bound regime, in place and two-step."""
     from btrirt_workloads import large_cavity
     out = {}
-    for prec, name in ((0, "fp64"), (1, "fp32s")):
-        case = dict(large_cavity(4096, 2048), precision=prec)
-        ctx = P.Context(device=0, max_slots=1)
-        slot = ctx.add(case)
-        ctx.step(slot, 10)
-        ms = time_steps(P, ctx, slot, steps)
-        ctx.close()
-        cells = 4096 * 2048
-        us = ms * 1e3 / steps
-        gbs = BYTES_PER_LU[prec] * cells / (us * 1e-6) / 1e9
-        out[name] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1), achieved_gbs=round(gbs, 1),
-                         frac=round(gbs / HBM_PEAK_GBS, 4))
+    for pattern, pname in ((P.LBM_PATTERN_AA, "in_place"), (P.LBM_PATTERN_AB, "two_step")):
+        for prec, name in ((0, "fp64"), (1, "fp32s")):
+            case = dict(large_cavity(4096, 2048), precision=prec, pattern=pattern)
+            ctx = P.Context(device=0, max_slots=1)
+            slot = ctx.add(case)
+            ctx.step(slot, 10)
+            ms = time_steps(P, ctx, slot, steps)
+            ctx.close()
+            cells = 4096 * 2048
+            us = ms * 1e3 / steps
+            gbs = BYTES_PER_LU[prec] * cells / (us * 1e-6) / 1e9
+            out[f"{pname}_{name}"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
+                                          achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
     log(f"hbm-bound 4096x2048: {out}")
     return out
 
@@ -285,6 +318,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--path", choices=["ab2", "aa"], default="ab2",
+                    help="ab2: two lattices, two steps per launch (default); aa: in place, one step per launch")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--tile", default="", help="bx,by,cpl,flags for the FP64 step kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -314,7 +349,7 @@ def main():
 
     if args.only:
         if args.only == "fp32":
-            res = fp32_variant(P, max(500, args.steps // 4))
+            res = fp32_variant(P, max(500, args.steps // 4), args.path)
         elif args.only == "batched":
             res = batched_variant(P, args.steps)
         elif args.only == "two_step":
@@ -325,11 +360,13 @@ def main():
         print(json.dumps({"only": args.only, **res}), flush=True)
         return
 
-    m = main_workload(P, args)
+    path = args.path
+    log(f"main: 2048x1024 FP64, {PATHS[path]['pattern']}, warmup {args.warmup}, steps {args.steps}")
+    m = run_cavity(P, path, args.steps, args.warmup, graph_chunk=args.graph_chunk, tile=args.tile)
+    log(f"main: {m['ms']:.1f} ms event, {m['wall'] * 1e3:.1f} ms wall, melt fraction "
+        f"{m['stats']['melt_fraction']:.6f}, Nu {m['stats']['nusselt']:.3f}, finite {m['stats']['finite']}, "
+        f"{len(m['series'])} reports, {m['launch_ms'] * 1e3:.2f} us/launch")
     mlups = m["cells"] * args.steps / (m["ms"] * 1e-3) / 1e6
-    kernel_s = m["kernel_ms"] * 1e-3
-    achieved = BYTES_PER_LU[0] * m["cells"] / kernel_s / 1e9
-    traffic = measured_traffic()
     out = {
         "metric": "MLUPS (flow+enthalpy) & % HBM roofline; batched vs plain; p50/p99 solve latency",
         "value": round(mlups, 1),
@@ -345,21 +382,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single cavity 2048x1024 D2Q9, FP64, Ra=1e8 Pr=1 Ste=1, heater W/4 centred, "
                                "from all-solid at Tm; diagnostics every 100 steps",
-                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": "in-place A-A"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "k_step<double,double,1>",
-                     "kernel_avg_us": round(m["kernel_ms"] * 1e3, 2),
-                     "algorithmic_bytes_per_launch": BYTES_PER_LU[0] * m["cells"]},
+                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": PATHS[path]["pattern"]},
+        "roofline": roofline(path, m),
         "melt_fraction": m["stats"]["melt_fraction"],
         "nusselt": m["stats"]["nusselt"],
         "budget_residual": m["stats"]["budget_residual"],
     }
     if not args.no_extras:
-        out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4))
+        if path != "aa":
+            out["in_place_aa"] = in_place_variant(P, max(1000, args.steps // 4))
+        out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4), path)
         out["hbm_bound_4096x2048"] = hbm_bound_variant(P)
-        out["two_step_two_lattice_fp64"] = two_step_variant(P)
         out["batched"] = batched_variant(P, 2000)
         try:
             from paper_1909_13086_amd import serve
