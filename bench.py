@@ -32,9 +32,9 @@ REPORT_EVERY = 100
 # traffic), counter summary, steps per launch
 CSRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc")
 PATHS = {
-    "ab2": dict(kernel="k_step2<double,double,4>", src=("lbm_device.h", "lbm_step2.hip"),
+    "ab2": dict(kernel="k_step2<double,double,true>", src=("lbm_device.h", "lbm_step2.hip"),
                 traffic=os.path.join(ROOT, "profiles", "traffic_k_step2_fp64_2048x1024.md"), per_launch=2,
-                pattern="two lattices, two steps per launch"),
+                pattern="two lattices, two steps per launch, rows staged through LDS"),
     "aa": dict(kernel="k_step<double,double,1>", src=("lbm_device.h", "lbm_step.hip"),
                traffic=os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md"), per_launch=1,
                pattern="in-place A-A, one step per launch"),
@@ -103,6 +103,7 @@ def run_cavity(P, path, steps, warmup, report_every=REPORT_EVERY, graph_chunk=0,
         bx, by, cpl, flags = (int(v) for v in tile.split(","))
         ctx.set_launch(0, bx, by, cpl, flags)
     slot = ctx.add(case)
+    seg = ctx.get_fusion(0)[1]
     if report_every:
         ctx.set_report(slot, report_every, (steps + warmup) // report_every + 2)
     ctx.step(slot, warmup)
@@ -121,7 +122,8 @@ def run_cavity(P, path, steps, warmup, report_every=REPORT_EVERY, graph_chunk=0,
     kms = time_steps(P, ctx, slot2, k2)
     ctx.close()
     per = PATHS[path]["per_launch"]
-    return dict(case=case, cells=cells, ms=ms, wall=wall, stats=st, series=series,
+    pattern = PATHS[path]["pattern"] + (f", {seg}-row segments" if path == "ab2" else "")
+    return dict(case=case, cells=cells, ms=ms, wall=wall, stats=st, series=series, pattern=pattern,
                 launch_ms=kms / k2 * per, launches=k2 // per, steps_per_launch=per)
 
 
@@ -152,11 +154,13 @@ def fp32_variant(P, steps, path="ab2"):
     ctx.step(slot, 100)
     ms = time_steps(P, ctx, slot, steps)
     st = ctx.reduce(slot)
+    seg = ctx.get_fusion(P.LBM_FP32_SHIFTED)[1]
     ctx.close()
     cells = case["nx"] * case["ny"]
     mlups = cells * steps / (ms * 1e-3) / 1e6
-    log(f"fp32s ({PATHS[path]['pattern']}): {mlups:.0f} MLUPS")
-    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=PATHS[path]["pattern"],
+    pattern = PATHS[path]["pattern"] + (f", {seg}-row segments" if path == "ab2" else "")
+    log(f"fp32s ({pattern}): {mlups:.0f} MLUPS")
+    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=pattern,
                 hbm_frac=round(mlups * 1e6 * BYTES_PER_LU[1] / (HBM_PEAK_GBS * 1e9), 4),
                 melt_fraction=st["melt_fraction"])
 
@@ -382,7 +386,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single cavity 2048x1024 D2Q9, FP64, Ra=1e8 Pr=1 Ste=1, heater W/4 centred, "
                                "from all-solid at Tm; diagnostics every 100 steps",
-                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": PATHS[path]["pattern"]},
+                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": m["pattern"]},
         "roofline": roofline(path, m),
         "melt_fraction": m["stats"]["melt_fraction"],
         "nusselt": m["stats"]["nusselt"],

@@ -202,22 +202,28 @@ int lbm_checkpoint_load(lbm_ctx *c, int slot, const void *host, size_t n);
 enum {
   LBM_LAUNCH_XCD_BANDS = 1,  /* each of the 8 XCDs gets a contiguous band of tiles */
   LBM_LAUNCH_NONTEMPORAL = 2, /* population loads/stores bypass cache retention */
-  LBM_LAUNCH_ALTERNATE = 4   /* tiles walked backwards on every other step */
+  LBM_LAUNCH_ALTERNATE = 4,  /* tiles walked backwards on every other step */
+  LBM_LAUNCH_ZIGZAG = 8,     /* two-step kernel: odd row segments walked downwards,
+                                so neighbouring segments share halo rows in the L2 */
+  LBM_LAUNCH_STAGED = 16     /* two-step kernel: rows copied into LDS one row ahead
+                                by asynchronous global-to-LDS loads */
 };
 /* Tile of the single-cavity step kernels for a precision: bx threads along x
  * (multiple of 64), by rows per block (bx*by <= 256), cpl rows per lane (1, 2
  * or 4) and LBM_LAUNCH_* flags.  Default 256, 1, 1,
- * LBM_LAUNCH_XCD_BANDS | LBM_LAUNCH_ALTERNATE.
+ * LBM_LAUNCH_XCD_BANDS | LBM_LAUNCH_ALTERNATE | LBM_LAUNCH_ZIGZAG | LBM_LAUNCH_STAGED.
  * Results do not depend on the tile or the flags. */
 int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags);
 int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags);
 /* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2 a
  * single launch advances a LBM_PATTERN_AB slot by two steps, reading its
  * lattice once and writing the other once (each wavefront walks a strip of
- * 62 columns up a segment of segment_rows rows, 4, 8, 16 or 32, keeping a
+ * 62 columns up a segment of segment_rows rows, 1 to 64, keeping a
  * three-row window of first-step values in registers).  Results equal those
- * of single steps bit for bit.  Default 2 steps per launch, 4-row segments. */
+ * of single steps bit for bit.  Default 2 steps per launch, segments of 2 rows
+ * (FP64) or 4 rows (FP32). */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
+int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
 int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
 /* Times the candidate tiles on a scratch cavity of the given size and

@@ -22,7 +22,9 @@ LBM_INIT_SOLID_AT_TM, LBM_INIT_LIQUID_T0, LBM_INIT_GAUSSIAN = 0, 1, 2
 LBM_FIELD_T, LBM_FIELD_FL, LBM_FIELD_H, LBM_FIELD_UX, LBM_FIELD_UY, LBM_FIELD_RHO = 1, 2, 4, 8, 16, 32
 FIELD_NAMES = ("T", "fl", "H", "ux", "uy", "rho")
 LBM_ALL = -1
-LBM_LAUNCH_XCD_BANDS, LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_ALTERNATE = 1, 2, 4
+LBM_LAUNCH_XCD_BANDS, LBM_LAUNCH_NONTEMPORAL, LBM_LAUNCH_ALTERNATE, LBM_LAUNCH_ZIGZAG = 1, 2, 4, 8
+LBM_LAUNCH_STAGED = 16
+LBM_LAUNCH_DEFAULT = LBM_LAUNCH_XCD_BANDS | LBM_LAUNCH_ALTERNATE | LBM_LAUNCH_ZIGZAG | LBM_LAUNCH_STAGED
 
 # Names exported by include/lbm.h and include/lbm_serve.h.
 EXPORTS = (
@@ -31,7 +33,7 @@ EXPORTS = (
     "lbm_fields", "lbm_set_report", "lbm_series", "lbm_state_load", "lbm_state_save",
     "lbm_set_launch", "lbm_get_launch", "lbm_set_graph_chunk", "lbm_autotune", "lbm_sync",
     "lbm_stream", "lbm_slot_info", "lbm_step_many", "lbm_set_group_bytes",
-    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_set_fusion",
+    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_set_fusion", "lbm_get_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
     "lbm_server_request", "lbm_server_summary",
 )
@@ -143,6 +145,8 @@ def lib():
             "lbm_get_launch": (ctypes.c_int, [vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4),
             "lbm_set_graph_chunk": (ctypes.c_int, [vp, ctypes.c_int]),
             "lbm_set_fusion": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "lbm_get_fusion": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]),
             "lbm_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p]),
             "lbm_sync": (ctypes.c_int, [vp]),
             "lbm_checkpoint_bytes": (ctypes.c_size_t, [vp, ctypes.c_int]),
@@ -291,7 +295,7 @@ def lbm_checkpoint_load(ctx, slot, blob):
 
 # ---- execution control --------------------------------------------------------
 
-def lbm_set_launch(ctx, precision, bx, by, cpl, flags=LBM_LAUNCH_XCD_BANDS | LBM_LAUNCH_ALTERNATE):
+def lbm_set_launch(ctx, precision, bx, by, cpl, flags=LBM_LAUNCH_DEFAULT):
     _check(lib().lbm_set_launch(ctx, int(precision), int(bx), int(by), int(cpl), int(flags)))
 
 
@@ -301,7 +305,15 @@ def lbm_get_launch(ctx, precision):
     return tuple(x.value for x in v)
 
 
-def lbm_set_fusion(ctx, precision, steps_per_launch, segment_rows=16):
+def lbm_get_fusion(ctx, precision):
+    n, seg = ctypes.c_int(), ctypes.c_int()
+    _check(lib().lbm_get_fusion(ctx, int(precision), ctypes.byref(n), ctypes.byref(seg)))
+    return n.value, seg.value
+
+
+def lbm_set_fusion(ctx, precision, steps_per_launch, segment_rows=None):
+    if segment_rows is None:
+        segment_rows = lbm_get_fusion(ctx, precision)[1]
     _check(lib().lbm_set_fusion(ctx, int(precision), int(steps_per_launch), int(segment_rows)))
 
 

@@ -98,11 +98,17 @@ class Context:
     def series(self, slot):
         return L.lbm_series(self.h, slot)
 
-    def set_launch(self, precision, bx, by, cpl, flags=L.LBM_LAUNCH_XCD_BANDS | L.LBM_LAUNCH_ALTERNATE):
+    def set_launch(self, precision, bx, by, cpl, flags=L.LBM_LAUNCH_DEFAULT):
         L.lbm_set_launch(self.h, precision, bx, by, cpl, flags)
 
-    def set_fusion(self, precision, steps_per_launch, segment_rows=16):
+    def get_launch(self, precision):
+        return L.lbm_get_launch(self.h, precision)
+
+    def set_fusion(self, precision, steps_per_launch, segment_rows=None):
         L.lbm_set_fusion(self.h, precision, steps_per_launch, segment_rows)
+
+    def get_fusion(self, precision):
+        return L.lbm_get_fusion(self.h, precision)
 
     def set_graph_chunk(self, chunk):
         L.lbm_set_graph_chunk(self.h, chunk)

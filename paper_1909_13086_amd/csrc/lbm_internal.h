@@ -49,9 +49,20 @@ struct LaunchCfg {
   int xcd = 1;  // contiguous tile bands per XCD
   int nt = 0;   // non-temporal population loads and stores
   int reverse = 1;  // walk tiles backwards on odd storage parity
+  int zigzag = 1;   // two-step kernel: odd segments walked downwards
+  int staged = 1;   // two-step kernel: rows copied into LDS one row ahead
   int fuse = 2;     // steps per launch of the two-lattice pattern (1 or 2)
   int seg = 4;      // rows per wavefront segment of the two-step kernel
 };
+constexpr int kMaxSegmentRows = 64;
+
+// Defaults per precision, the fastest measured on MI355X at 2048x1024 and
+// 4096x2048: two-step segments of 2 rows in FP64, 4 rows in FP32.
+inline LaunchCfg default_launch(int precision) {
+  LaunchCfg L;
+  L.seg = precision == 0 ? 2 : 4;
+  return L;
+}
 
 // Accumulators of one reduction, FP64.
 enum RedSlot {

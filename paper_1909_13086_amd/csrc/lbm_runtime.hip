@@ -218,7 +218,7 @@ struct lbm_ctx {
   StatsDev *stats_host = nullptr;  // pinned, 2 entries: current state and state at load
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
-  LaunchCfg launch[2];
+  LaunchCfg launch[2] = {lbm::default_launch(0), lbm::default_launch(1)};
   int graph_chunk = 0;
   int num_cus = 256;
   size_t group_bytes = size_t(160) << 20;  // cache-group capacity of the batched launch
@@ -985,6 +985,8 @@ int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags
   L.xcd = (flags & LBM_LAUNCH_XCD_BANDS) ? 1 : 0;
   L.nt = (flags & LBM_LAUNCH_NONTEMPORAL) ? 1 : 0;
   L.reverse = (flags & LBM_LAUNCH_ALTERNATE) ? 1 : 0;
+  L.zigzag = (flags & LBM_LAUNCH_ZIGZAG) ? 1 : 0;
+  L.staged = (flags & LBM_LAUNCH_STAGED) ? 1 : 0;
   for (auto &s : c->slots) drop_graphs(s);
   return LBM_OK;
 }
@@ -997,19 +999,28 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
   *by = L.by;
   *cpl = L.cpl;
   *flags = (L.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (L.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
-           (L.reverse ? LBM_LAUNCH_ALTERNATE : 0);
+           (L.reverse ? LBM_LAUNCH_ALTERNATE : 0) | (L.zigzag ? LBM_LAUNCH_ZIGZAG : 0) |
+           (L.staged ? LBM_LAUNCH_STAGED : 0);
   return LBM_OK;
 }
 
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
-  if ((steps_per_launch != 1 && steps_per_launch != 2) ||
-      (segment_rows != 4 && segment_rows != 8 && segment_rows != 16 && segment_rows != 32))
-    return fail(LBM_EINVAL, "steps per launch in {1, 2}, segment rows in {4, 8, 16, 32}");
+  if ((steps_per_launch != 1 && steps_per_launch != 2) || segment_rows < 1 ||
+      segment_rows > lbm::kMaxSegmentRows)
+    return fail(LBM_EINVAL, "steps per launch in {1, 2}, segment rows in 1..64");
   c->launch[precision].fuse = steps_per_launch;
   c->launch[precision].seg = segment_rows;
   for (auto &s : c->slots) drop_graphs(s);
+  return LBM_OK;
+}
+
+int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows) {
+  if (!c || !steps_per_launch || !segment_rows) return fail(LBM_EINVAL, "NULL argument");
+  if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
+  *steps_per_launch = c->launch[precision].fuse;
+  *segment_rows = c->launch[precision].seg;
   return LBM_OK;
 }
 
@@ -1191,9 +1202,12 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
     c->launch[precision] = saved;
     return rc;
   }
+  // the segment walk and row staging belong to the two-step kernel: kept
   const int best_flags = (best.xcd ? LBM_LAUNCH_XCD_BANDS : 0) |
                          (best.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
-                         (best.reverse ? LBM_LAUNCH_ALTERNATE : 0);
+                         (best.reverse ? LBM_LAUNCH_ALTERNATE : 0) |
+                         (saved.zigzag ? LBM_LAUNCH_ZIGZAG : 0) |
+                         (saved.staged ? LBM_LAUNCH_STAGED : 0);
   cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best_flags,
                 1000.0 * best_ms / reps};
   write_cache(cache_path, cache);

@@ -3,20 +3,28 @@
 // One launch reads the natural state at time t from lattice A once and writes
 // the natural state at t+2 to lattice B once, so a pair of steps moves the
 // bytes of one.  Each wavefront owns a strip of 62 columns and a segment of
-// SEG rows and walks up the segment with a three-row window in registers:
-//   - first step ("P1", a collision of the loaded state) for rows y0-1 .. y1,
-//     columns x0-1 .. x0+62 (one halo column/row on each side, recomputed by
-//     the neighbouring wavefronts as well);
+// `seg` rows and walks along the segment with a three-row window in
+// registers:
+//   - first step (a collision of the loaded state) for the segment's rows and
+//     one halo row on each side, columns x0-1 .. x0+62 (the halo cells are
+//     recomputed by the neighbouring wavefronts as well);
 //   - second step for the owned cells: the streamed populations are taken
 //     from the window (from the neighbouring lane for x shifts, a wavefront
 //     shuffle), walls reflect into the cell's own first-step values exactly as
 //     the single-step kernels do, the collision runs again and the result is
 //     scattered to B.
-// Only registers and lane shuffles hold the intermediate state; nothing is
-// staged in memory between the two steps.  Every collision is the same code
-// as in the single-step kernels, so a launch equals two single two-lattice
-// steps bit for bit.
+// Every collision is the same code as in the single-step kernels, so a launch
+// equals two single two-lattice steps bit for bit.
+//
+// Rows reach the registers in one of two ways:
+//   - direct: each row is loaded from A when the walk needs it;
+//   - staged: rows are copied from A into a per-wavefront LDS double buffer by
+//     asynchronous global-to-LDS loads issued one row ahead, so the fetch of
+//     the next row overlaps the two collisions of the current one without
+//     holding registers.
 #include "lbm_device.h"
+
+#include <utility>
 
 namespace lbm {
 namespace {
@@ -24,9 +32,15 @@ namespace {
 using namespace dev;
 
 constexpr int kStripCols = kWave - 2;  // owned columns per wavefront
+constexpr int kDirectWaves = 4;        // wavefronts per workgroup, direct rows
+constexpr int kStagedWaves = 2;        // wavefronts per workgroup, staged rows
 
-// Populations going up (c_y = +1): 2, 5, 6 -> slots 0, 1, 2 of the window.
-__device__ constexpr int up_slot(int i) { return i == 2 ? 0 : (i == 5 ? 1 : 2); }
+// The three populations that move along the walk direction D (c_y = D):
+// 2, 5, 6 going up, 4, 7, 8 going down -> window slots 0, 1, 2.
+template <int D>
+__device__ constexpr int along_slot(int i) {
+  return D > 0 ? (i == 2 ? 0 : (i == 5 ? 1 : 2)) : (i == 4 ? 0 : (i == 7 ? 1 : 2));
+}
 
 template <typename R>
 __device__ __forceinline__ R lane_from(R v, int dx) {
@@ -36,133 +50,358 @@ __device__ __forceinline__ R lane_from(R v, int dx) {
   return v;
 }
 
-template <typename S, typename R, int SEG>
-__global__ __launch_bounds__(256) void k_step2(CavDev c, int strips_x, int nseg, int order) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
-  const int w = b * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (w >= strips_x * nseg) return;  // uniform per wavefront; no barriers follow
-  const int strip = w % strips_x, seg = w / strips_x;
-  const int x = strip * kStripCols - 1 + lane;
-  const int y0 = seg * SEG;
-  const int y1 = min(y0 + SEG, c.ny);
+// Column of one lane of a strip.
+struct Col {
+  int x, xw;          // column (-1 .. nx) and its periodic wrap
+  bool real;          // the column exists (owners, and halo columns that wrap)
+  bool owner;         // lanes 1 .. 62 inside the cavity
+  bool bottom_hot;    // heated column of a non-periodic bottom wall
+  bool strip_flux;    // counts the first-step strip flux of row 0
+};
+
+__device__ __forceinline__ bool col_real(const CavDev &c, int x) {
   // only columns -1 .. nx matter (owners are 0 .. nx-1); with periodic sides
   // the halo columns -1 and nx wrap once
-  const bool x_real = (x >= 0 && x < c.nx) || (c.periodic_x && (x == -1 || x == c.nx));
-  const int xw = x < 0 ? x + c.nx : (x >= c.nx ? x - c.nx : x);
-  const bool owner = lane >= 1 && lane <= kStripCols && x < c.nx;
-  const bool bottom_hot = !c.periodic_y && x >= c.hlo && x <= c.hhi;
-  const Coef<R> k(c);
-  const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
-  S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
+  return (x >= 0 && x < c.nx) || (c.periodic_x && (x == -1 || x == c.nx));
+}
+__device__ __forceinline__ int col_wrap(const CavDev &c, int x) {
+  return x < 0 ? x + c.nx : (x >= c.nx ? x - c.nx : x);
+}
+__device__ __forceinline__ bool row_real(const CavDev &c, int r) {
+  return (r >= 0 && r < c.ny) || (c.periodic_y && (r == -1 || r == c.ny));
+}
+__device__ __forceinline__ int row_wrap(const CavDev &c, int r) {
+  return r < 0 ? r + c.ny : (r >= c.ny ? r - c.ny : r);
+}
 
-  // first step of row r: the loaded natural state collided (zeros when the
-  // row or column does not exist; such values are never used)
-  auto first_step = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
-    const bool r_real = (r >= 0 && r < c.ny) || (c.periodic_y && (r == -1 || r == c.ny));
-    if (!(r_real && x_real)) {
+__device__ __forceinline__ Col make_col(const CavDev &c, int x, int lane, int y0) {
+  Col q;
+  q.x = x;
+  q.real = col_real(c, x);
+  q.xw = col_wrap(c, x);
+  q.owner = lane >= 1 && lane <= kStripCols && x < c.nx;
+  q.bottom_hot = !c.periodic_y && x >= c.hlo && x <= c.hhi;
+  // the segment that owns row 0 computes that row's first step exactly once
+  q.strip_flux = q.owner && q.bottom_hot && y0 == 0;
+  return q;
+}
+
+// First step of a loaded row: collision, plus the strip flux of a heated
+// bottom cell's first step.
+template <typename R>
+__device__ __forceinline__ void first_collide(const CavDev &c, const Coef<R> &k, const Col &q, int r,
+                                              R (&f)[kQ], R (&g)[kQ]) {
+  collide<R>(k, f, g);
+  if (r == 0 && q.strip_flux) add_strip_flux<R>(c, k, q.x, g);
+}
+
+template <typename R>
+__device__ __forceinline__ void zero_row(R (&f)[kQ], R (&g)[kQ]) {
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) f[i] = g[i] = R(0);
-      return;
-    }
-    const int rw = r < 0 ? r + c.ny : (r >= c.ny ? r - c.ny : r);
-    load_natural<S, R>(A, c.plane, cell_base(c, xw, rw), f, g);
-    collide<R>(k, f, g);
-  };
+  for (int i = 0; i < kQ; ++i) f[i] = g[i] = R(0);
+}
 
-  R cf[kQ], cg[kQ];      // first-step state of row y
-  R nf[kQ], ng[kQ];      // first-step state of row y + 1
-  R uf[3], ug[3];        // upward populations of row y - 1
-  {
-    R tf[kQ], tg[kQ];
-    first_step(y0 - 1, tf, tg);
-    uf[0] = tf[2]; uf[1] = tf[5]; uf[2] = tf[6];
-    ug[0] = tg[2]; ug[1] = tg[5]; ug[2] = tg[6];
+// Second step of row y: the streamed state gathered from the window, walls
+// applied, then collided (result in pf, pg).
+template <typename R, int D>
+__device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k, const Col &q, int y,
+                                               const R (&cf)[kQ], const R (&cg)[kQ],
+                                               const R (&nf)[kQ], const R (&ng)[kQ],
+                                               const R (&af)[3], const R (&ag)[3], R (&pf)[kQ],
+                                               R (&pg)[kQ]) {
+  const bool xm_in = c.periodic_x || q.x - 1 >= 0;
+  const bool xp_in = c.periodic_x || q.x + 1 < c.nx;
+  const bool ym_in = c.periodic_y || y - 1 >= 0;
+  const bool yp_in = c.periodic_y || y + 1 < c.ny;
+  const bool hot = q.bottom_hot && y == 0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int ex = cx(i), ey = cy(i);
+    R vf, vg;
+    if (ey == 0) {
+      vf = cf[i];
+      vg = cg[i];
+    } else if (ey == D) {
+      vf = af[along_slot<D>(i)];
+      vg = ag[along_slot<D>(i)];
+    } else {
+      vf = nf[i];
+      vg = ng[i];
+    }
+    vf = lane_from(vf, ex);
+    vg = lane_from(vg, ex);
+    const bool in_x = ex > 0 ? xm_in : (ex < 0 ? xp_in : true);
+    const bool in_y = ey > 0 ? ym_in : (ey < 0 ? yp_in : true);
+    if (!(in_x && in_y)) {
+      // the link crossed a wall: it comes back from the cell itself
+      vf = cf[opp(i)];
+      vg = cg[opp(i)];
+      if (ey == 1 && hot) vg = k.anti(i) - vg;
+    }
+    pf[i] = vf;
+    pg[i] = vg;
   }
-  first_step(y0, cf, cg);
-  if (y0 == 0 && owner && bottom_hot) add_strip_flux<R>(c, k, x, cg);
+  collide<R>(k, pf, pg);
+}
 
-  for (int y = y0; y < y1; ++y) {
-    first_step(y + 1, nf, ng);
-    // streamed (pre-collision) state of row y at t+1
-    const bool xm_in = c.periodic_x || x - 1 >= 0;
-    const bool xp_in = c.periodic_x || x + 1 < c.nx;
-    const bool ym_in = c.periodic_y || y - 1 >= 0;
-    const bool yp_in = c.periodic_y || y + 1 < c.ny;
-    const bool hot = bottom_hot && y == 0;
-    R pf[kQ], pg[kQ];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const int ex = cx(i), ey = cy(i);
-      R vf, vg;
-      if (ey == 0) {
-        vf = cf[i];
-        vg = cg[i];
-      } else if (ey > 0) {
-        vf = uf[up_slot(i)];
-        vg = ug[up_slot(i)];
-      } else {
-        vf = nf[i];
-        vg = ng[i];
-      }
-      vf = lane_from(vf, ex);
-      vg = lane_from(vg, ex);
-      const bool in_x = ex > 0 ? xm_in : (ex < 0 ? xp_in : true);
-      const bool in_y = ey > 0 ? ym_in : (ey < 0 ? yp_in : true);
-      if (!(in_x && in_y)) {
-        // the link crossed a wall: it comes back from the cell itself
-        vf = cf[opp(i)];
-        vg = cg[opp(i)];
-        if (ey == 1 && hot) vg = k.anti(i) - vg;
-      }
-      pf[i] = vf;
-      pg[i] = vg;
-    }
-    // second step: collide and stream into B
-    collide<R>(k, pf, pg);
-    if (owner) {
-      store_scatter<S, R>(c, k, B, x, y, cell_base(c, x, y), pf, pg);
-      if (hot) add_strip_flux<R>(c, k, x, pg);
-    }
-    // slide the window up by one row
-    uf[0] = cf[2]; uf[1] = cf[5]; uf[2] = cf[6];
-    ug[0] = cg[2]; ug[1] = cg[5]; ug[2] = cg[6];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      cf[i] = nf[i];
-      cg[i] = ng[i];
-    }
+// Stores of an owned cell's second step (and its strip flux).
+template <typename S, typename R>
+__device__ __forceinline__ void emit(const CavDev &c, const Coef<R> &k, S *__restrict__ B, const Col &q,
+                                     int y, const R (&pf)[kQ], const R (&pg)[kQ]) {
+  if (q.owner) {
+    store_scatter<S, R>(c, k, B, q.x, y, cell_base(c, q.x, y), pf, pg);
+    if (q.bottom_hot && y == 0) add_strip_flux<R>(c, k, q.x, pg);
   }
 }
 
-template <typename S, typename R, int SEG>
-hipError_t dispatch_seg(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
-  const int strips_x = (c.nx + kStripCols - 1) / kStripCols;
-  const int nseg = (c.ny + SEG - 1) / SEG;
-  const int waves = strips_x * nseg;
-  const int per_block = 4;
-  const dim3 grid((waves + per_block - 1) / per_block);
-  const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0);
-  hipLaunchKernelGGL((k_step2<S, R, SEG>), grid, dim3(per_block * kWave), 0, s, c, strips_x,
-                     nseg, order);
-  return hipGetLastError();
+// Window slide: (a, c) <- (populations of c moving along D, n).
+template <int D, typename R>
+__device__ __forceinline__ void slide(R (&af)[3], R (&ag)[3], R (&cf)[kQ], R (&cg)[kQ],
+                                      const R (&nf)[kQ], const R (&ng)[kQ]) {
+  constexpr int a0 = D > 0 ? 2 : 4, a1 = D > 0 ? 5 : 7, a2 = D > 0 ? 6 : 8;
+  af[0] = cf[a0]; af[1] = cf[a1]; af[2] = cf[a2];
+  ag[0] = cg[a0]; ag[1] = cg[a1]; ag[2] = cg[a2];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    cf[i] = nf[i];
+    cg[i] = ng[i];
+  }
+}
+
+// Rows y0 .. y1-1 of one strip, walked in direction D (+1 upwards from y0,
+// -1 downwards from y1-1), each row loaded from A when needed.  Adjacent
+// segments walking in opposite directions reach the two halo rows they share
+// at the same point of their walks, so the second reader finds them in L2.
+template <typename S, typename R, int D>
+__device__ __forceinline__ void walk_direct(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+                                            S *__restrict__ B, const Col &q, int y0, int y1) {
+  auto first_step = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
+    // zeros when the row or column does not exist; such values are never used
+    if (!(row_real(c, r) && q.real)) {
+      zero_row(f, g);
+      return;
+    }
+    load_natural<S, R>(A, c.plane, cell_base(c, q.xw, row_wrap(c, r)), f, g);
+    first_collide<R>(c, k, q, r, f, g);
+  };
+  const int ys = D > 0 ? y0 : y1 - 1;
+  const int ye = D > 0 ? y1 : y0 - 1;
+  R cf[kQ], cg[kQ];      // first-step state of row y
+  R nf[kQ], ng[kQ];      // first-step state of row y + D
+  R af[3], ag[3];        // populations of row y - D moving along the walk
+  first_step(ys - D, cf, cg);
+  first_step(ys, nf, ng);
+  slide<D>(af, ag, cf, cg, nf, ng);
+  for (int y = ys; y != ye; y += D) {
+    first_step(y + D, nf, ng);
+    R pf[kQ], pg[kQ];
+    second_collide<R, D>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
+    emit<S, R>(c, k, B, q, y, pf, pg);
+    slide<D>(af, ag, cf, cg, nf, ng);
+  }
+}
+
+// ---- staged rows --------------------------------------------------------
+
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVm0 = 0x0F70;    // vector memory count 0, others unconstrained
+constexpr int kWaitLgkm0 = 0xC07F;  // LDS/scalar count 0, others unconstrained
+
+__device__ __forceinline__ void wait_vm() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void wait_lgkm() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+  asm volatile("" ::: "memory");
+}
+
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_addr(T *p) {
+  return (__attribute__((address_space(3))) void *)p;
+}
+
+// Global-to-LDS copy lanes of a strip row.  The copy moves 4 bytes per lane
+// and instruction and writes lane l's bytes at LDS offset 4 l: FP32 rows take
+// one instruction per plane (lane l copies cell l), FP64 rows two (lanes 2m
+// and 2m+1 copy the low and high words of cell m of each half row).  Lanes
+// whose cell does not exist copy the row's first cell instead, so every copy
+// stays inside the lattice; the lanes of such cells never read their slots.
+struct CopyLanes {
+  uint32_t off[2];  // byte offset of the copied word within the row
+};
+
+template <typename S>
+__device__ __forceinline__ CopyLanes copy_lanes(const CavDev &c, int x0, int lane) {
+  CopyLanes L;
+  const uint32_t sub = sizeof(S) == 8 ? 4u * (lane & 1) : 0u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int m = sizeof(S) == 8 ? h * (kWave / 2) + (lane >> 1) : lane;
+    const int x = x0 - 1 + m;
+    const uint32_t e = col_real(c, x) ? (uint32_t)cell_base(c, col_wrap(c, x), 0) : 0u;
+    L.off[h] = e * (uint32_t)sizeof(S) + sub;
+  }
+  return L;
+}
+
+// Copy of plane I of a row.  The instruction's immediate offset moves the
+// global and the LDS address together; it is kept below 4096 bytes by
+// stepping both bases once per group of planes.
+template <typename S, int I>
+__device__ __forceinline__ void copy_plane(const char *base, const CopyLanes &L, S *buf) {
+  constexpr int plane_bytes = kWave * sizeof(S);
+  constexpr int per_group = 4096 / plane_bytes;
+  constexpr int group_bytes = per_group * plane_bytes;
+  constexpr int grp = I / per_group, imm = (I % per_group) * plane_bytes;
+  const char *g = base + grp * group_bytes;
+  S *l = buf + grp * (group_bytes / (int)sizeof(S));
+  if constexpr (sizeof(S) == 8) {
+    __builtin_amdgcn_global_load_lds(g + L.off[0], lds_addr(l), 4, imm, 0);
+    __builtin_amdgcn_global_load_lds(g + L.off[1], lds_addr(l + kWave / 2), 4, imm, 0);
+  } else {
+    __builtin_amdgcn_global_load_lds(g + L.off[0], lds_addr(l), 4, imm, 0);
+  }
+}
+
+template <typename S, int... I>
+__device__ __forceinline__ void copy_planes(const char *base, const CopyLanes &L, S *buf,
+                                            std::integer_sequence<int, I...>) {
+  (copy_plane<S, I>(base, L, buf), ...);
+}
+
+// Issue the copy of row r of A into an LDS buffer of kPlanes x kWave values.
+template <typename S>
+__device__ __forceinline__ void copy_row(const CavDev &c, const S *__restrict__ A, const CopyLanes &L,
+                                         int r, S *buf) {
+  const int64_t row = (int64_t)row_wrap(c, r) * (c.pitch >> 6) * (kPlanes * kWave);
+  const char *base = reinterpret_cast<const char *>(A + row);
+  asm volatile("" ::: "memory");
+  copy_planes<S>(base, L, buf, std::make_integer_sequence<int, kPlanes>{});
+  asm volatile("" ::: "memory");
 }
 
 template <typename S, typename R>
-hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
-  switch (cfg.seg) {
-    case 4: return dispatch_seg<S, R, 4>(c, cfg, s);
-    case 8: return dispatch_seg<S, R, 8>(c, cfg, s);
-    case 16: return dispatch_seg<S, R, 16>(c, cfg, s);
-    case 32: return dispatch_seg<S, R, 32>(c, cfg, s);
-    default: return hipErrorInvalidValue;
+__device__ __forceinline__ void read_row(const S *buf, int lane, R (&f)[kQ], R (&g)[kQ]) {
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    f[i] = R(buf[i * kWave + lane]);
+    g[i] = R(buf[(kQ + i) * kWave + lane]);
   }
+}
+
+// The same walk with rows staged through LDS.  Rows along the walk are
+// numbered k = 0 (ys - D), 1 (ys), 2, ...; row k lives in buffer k & 1.  The
+// copy of row k + 1 is issued into the buffer that row k - 1 has left, before
+// row k is read and collided; it is waited for before the stores of that
+// iteration are issued, so the stores never delay a later wait.
+template <typename S, typename R, int D>
+__device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+                                            S *__restrict__ B, const Col &q, int y0, int y1, int x0,
+                                            S *bufs) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const CopyLanes L = copy_lanes<S>(c, x0, lane);
+  auto buf = [&](int b) { return bufs + b * (kPlanes * kWave); };
+  auto issue = [&](int r, int b) {
+    if (row_real(c, r)) copy_row<S>(c, A, L, r, buf(b));
+  };
+  auto first_step = [&](int r, int b, R (&f)[kQ], R (&g)[kQ]) {
+    // zeros when the row or column does not exist; such values are never used
+    if (!(row_real(c, r) && q.real)) {
+      zero_row(f, g);
+      return;
+    }
+    read_row<S, R>(buf(b), lane, f, g);
+    first_collide<R>(c, k, q, r, f, g);
+  };
+
+  const int ys = D > 0 ? y0 : y1 - 1;
+  const int ye = D > 0 ? y1 : y0 - 1;
+  R cf[kQ], cg[kQ];      // first-step state of row y
+  R nf[kQ], ng[kQ];      // first-step state of row y + D
+  R af[3], ag[3];        // populations of row y - D moving along the walk
+  issue(ys - D, 0);
+  issue(ys, 1);
+  wait_vm();
+  first_step(ys - D, 0, cf, cg);
+  wait_lgkm();           // buffer 0 has been read before it is refilled
+  issue(ys + D, 0);
+  first_step(ys, 1, nf, ng);
+  slide<D>(af, ag, cf, cg, nf, ng);
+  wait_vm();
+  int b = 0;
+  for (int y = ys; y != ye; y += D, b ^= 1) {
+    wait_lgkm();         // buffer b ^ 1 (row y) has been read
+    if (y + D != ye) issue(y + 2 * D, b ^ 1);
+    first_step(y + D, b, nf, ng);
+    R pf[kQ], pg[kQ];
+    second_collide<R, D>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
+    wait_vm();
+    emit<S, R>(c, k, B, q, y, pf, pg);
+    slide<D>(af, ag, cf, cg, nf, ng);
+  }
+}
+
+// order: bit 0 XCD bands, bit 1 tiles walked backwards on odd parity,
+// bit 2 odd segments walked downwards
+template <typename S, typename R, bool STAGED>
+__global__ __launch_bounds__(STAGED ? kStagedWaves * kWave : kDirectWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(2))) void k_step2(
+    CavDev c, int strips_x, int nseg, int seg_rows, int order) {
+  constexpr int waves = STAGED ? kStagedWaves : kDirectWaves;
+  __shared__ S lds[STAGED ? waves * 2 * kPlanes * kWave : 1];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
+  const int w = b * waves + wid;
+  if (w >= strips_x * nseg) return;  // uniform per wavefront; no barriers follow
+  const int strip = w % strips_x, seg = w / strips_x;
+  const int x0 = strip * kStripCols;
+  const int y0 = seg * seg_rows;
+  const int y1 = min(y0 + seg_rows, c.ny);
+  const Col q = make_col(c, x0 - 1 + lane, lane, y0);
+  const Coef<R> k(c);
+  const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
+  S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
+  const bool down = (order & 4) && (seg & 1);
+  if constexpr (STAGED) {
+    S *bufs = lds + wid * 2 * kPlanes * kWave;
+    if (down)
+      walk_staged<S, R, -1>(c, k, A, B, q, y0, y1, x0, bufs);
+    else
+      walk_staged<S, R, +1>(c, k, A, B, q, y0, y1, x0, bufs);
+  } else {
+    if (down)
+      walk_direct<S, R, -1>(c, k, A, B, q, y0, y1);
+    else
+      walk_direct<S, R, +1>(c, k, A, B, q, y0, y1);
+  }
+}
+
+template <typename S, typename R, bool STAGED>
+hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
+  if (cfg.seg < 1 || cfg.seg > kMaxSegmentRows) return hipErrorInvalidValue;
+  const int strips_x = (c.nx + kStripCols - 1) / kStripCols;
+  const int nseg = (c.ny + cfg.seg - 1) / cfg.seg;
+  const int waves = strips_x * nseg;
+  const int per_block = STAGED ? kStagedWaves : kDirectWaves;
+  const dim3 grid((waves + per_block - 1) / per_block);
+  const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
+  hipLaunchKernelGGL((k_step2<S, R, STAGED>), grid, dim3(per_block * kWave), 0, s, c, strips_x, nseg,
+                     cfg.seg, order);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {
-  return precision == 0 ? dispatch<double, double>(c, cfg, s) : dispatch<float, float>(c, cfg, s);
+  if (cfg.staged)
+    return precision == 0 ? dispatch<double, double, true>(c, cfg, s)
+                          : dispatch<float, float, true>(c, cfg, s);
+  return precision == 0 ? dispatch<double, double, false>(c, cfg, s)
+                        : dispatch<float, float, false>(c, cfg, s);
 }
 
 }  // namespace lbm

@@ -140,12 +140,16 @@ def test_patterns_and_tiles_agree_bitwise(ctx, P, steps):
     f0, g0 = _random_state(9, 128, 64)
     ref = _run_state(ctx, P, dict(base, pattern=P.LBM_PATTERN_AB), steps, f0, g0)
     # (bx, by, cpl, flags): flags bit 0 = XCD bands, bit 1 = non-temporal access,
-    # bit 2 = tiles walked backwards on every other step
+    # bit 2 = tiles walked backwards on every other step, bit 3 = zigzag
+    # segment walk of the two-step kernel (no effect on the in-place pattern)
     for launch in [(256, 1, 1, 1), (64, 4, 2, 0), (128, 2, 4, 1), (64, 1, 1, 0), (256, 1, 1, 3), (128, 2, 2, 2),
-                   (64, 1, 1, 5), (128, 2, 2, 4), (64, 4, 1, 7)]:
+                   (64, 1, 1, 5), (128, 2, 2, 4), (64, 4, 1, 7), (64, 4, 1, 15)]:
         got = _run_state(ctx, P, dict(base), steps, f0, g0, launch)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), launch
-    ctx.set_launch(0, 256, 1, 1, 5)
+    for flags in (0, 5, 8, 13, 16, 29):
+        got = _run_state(ctx, P, dict(base, pattern=P.LBM_PATTERN_AB), steps, f0, g0, (256, 1, 1, flags))
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), flags
+    ctx.set_launch(0, 256, 1, 1, P.LBM_LAUNCH_DEFAULT)
 
 
 def test_graph_chunks_equal_plain_launches(ctx, P):
@@ -244,7 +248,8 @@ FUSED_GEOMS = GEOMS + [(130, 70, 0, 0, 0.4, 0.3), (200, 37, 1, 1, 0.5, 0.25), (6
 
 
 @pytest.mark.parametrize("geom", FUSED_GEOMS, ids=[f"{g[0]}x{g[1]}p{g[2]}{g[3]}" for g in FUSED_GEOMS])
-@pytest.mark.parametrize("prec,seg,steps", [(0, 8, 2), (0, 16, 7), (1, 32, 6), (0, 32, 13), (1, 8, 5)])
+@pytest.mark.parametrize("prec,seg,steps", [(0, 8, 2), (0, 16, 7), (1, 32, 6), (0, 32, 13), (1, 8, 5),
+                                             (0, 6, 4), (1, 5, 3), (0, 1, 2), (0, 3, 5), (1, 64, 4)])
 def test_two_step_kernel_equals_single_steps(P, geom, prec, seg, steps):
     nx, ny, px, py, hc, hw = geom
     case = dict(cavity(nx, ny, periodic_x=px, periodic_y=py, heater_center=hc, heater_width=hw,
@@ -254,17 +259,22 @@ def test_two_step_kernel_equals_single_steps(P, geom, prec, seg, steps):
     print(f"case two-step {nx}x{ny} periodic=({px},{py}) prec={prec} seg={seg} steps={steps}", flush=True)
     f0, g0 = _random_state(2000 + nx + ny, nx, ny)
     out = []
-    for fuse in (1, 2):
+    # single steps, two-step launches with the zigzag segment walk (default)
+    # and with every segment walked upwards, rows loaded directly or staged
+    for fuse, flags in ((1, P.LBM_LAUNCH_DEFAULT), (2, P.LBM_LAUNCH_DEFAULT), (2, 5), (2, 5 | P.LBM_LAUNCH_STAGED),
+                        (2, 13 | P.LBM_LAUNCH_STAGED)):
         with P.Context(device=0, max_slots=1) as ctx:
             ctx.set_fusion(prec, fuse, seg)
+            ctx.set_launch(prec, 256, 1, 1, flags)
             s = ctx.add(case)
             ctx.state_load(s, f0, g0)
             ctx.step(s, steps)
             out.append((ctx.state_save(s), ctx.reduce(s)))
-    (a, sa), (b, sb) = out
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    for k in ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "budget_residual"):
-        assert sa[k] == sb[k], k
+    a, sa = out[0]
+    for b, sb in out[1:]:
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        for k in ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "budget_residual"):
+            assert sa[k] == sb[k], k
 
 
 @pytest.mark.parametrize("chunk", [7, 10])
@@ -291,8 +301,9 @@ def test_two_step_kernel_full_size_matches_oracle(P):
     case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB)
     print("case 2048x1024 FP64 two-step kernel, 6 steps vs oracle", flush=True)
     f0, g0 = _random_state(23, 2048, 1024)
-    with P.Context(device=0, max_slots=1) as ctx:
-        ctx.set_fusion(0, 2, 16)
+    with P.Context(device=0, max_slots=1) as ctx:  # default launch configuration
+        assert ctx.get_fusion(0) == (2, 2)
+        assert ctx.get_launch(0)[3] == P.LBM_LAUNCH_DEFAULT
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)
         ctx.step(s, 6)
