@@ -248,6 +248,26 @@ def batched_variant(P, steps, chunk=100):
     return res
 
 
+def serving_study(P):
+    """The full serving workload (256 seeded Poisson requests at 20/s, sizes
+    256x128 ... 2048x1024, 1000-50000 steps, FP64 / FP32-shifted 50/50, 16 GB
+    budget), whose offered load is far above the device's, then the first 64
+    requests of the same trace at an arrival rate that offers 70 % of the
+    throughput the full run sustained."""
+    from paper_1909_13086_amd import serve
+    from btrirt_workloads import serving_trace
+    full = serve.bench_serving(P, n=256, steps_hi=50000, progress_every=16)
+    log(f"serving, full trace: {full}")
+    n70 = 64
+    tr = serving_trace(seed=5, n=n70, steps_hi=50000)
+    mean_lu = sum(r["case"]["nx"] * r["case"]["ny"] * r["steps"] for r in tr) / n70
+    rate = 0.7 * full["mlups"] * 1e6 / mean_lu
+    at70 = serve.bench_serving(P, n=n70, rate=rate, steps_hi=50000, progress_every=8)
+    at70["offered_mlups"] = round(rate * mean_lu / 1e6, 1)
+    log(f"serving at 70 % of capacity: {at70}")
+    return dict(full=full, at_70_percent=at70)
+
+
 def cpu_baseline(target_s):
     """The FP64 oracle on the host cores, on the same 2048x1024 cavity, for
     as many whole steps as fit in about target_s seconds."""
@@ -330,7 +350,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
-    ap.add_argument("--only", choices=["fp32", "batched", "serving", "two_step"], default="",
+    ap.add_argument("--only", choices=["fp32", "batched", "serving", "serving_study", "two_step"], default="",
                     help="run one variant alone (for profiling) and print its result")
     ap.add_argument("--study", choices=["heater"], default="",
                     help="run the heater-position study of the cavity section instead of the benchmark")
@@ -358,6 +378,8 @@ def main():
             res = batched_variant(P, args.steps)
         elif args.only == "two_step":
             res = two_step_variant(P, args.steps)
+        elif args.only == "serving_study":
+            res = serving_study(P)
         else:
             from paper_1909_13086_amd import serve
             res = serve.bench_serving(P)

@@ -68,6 +68,12 @@ int lbm_server_submit(lbm_server *s, const lbm_case *cs, int64_t steps, double a
  * runs arrivals twice as fast) and returns when every request has finished,
  * failed or been rejected.  Blocks. */
 int lbm_server_run(lbm_server *s, double time_scale);
+/* Called by lbm_server_run, on its thread, each time a request leaves the
+ * loop (done, failed or rejected), with the request's final record; user is
+ * passed through.  The callback must not call into the server.  fn = NULL
+ * removes it.  Set before lbm_server_run. */
+typedef void (*lbm_request_fn)(const lbm_request *r, void *user);
+int lbm_server_on_finish(lbm_server *s, lbm_request_fn fn, void *user);
 int lbm_server_request(lbm_server *s, int32_t id, lbm_request *out);
 int lbm_server_summary(lbm_server *s, lbm_serve_summary *out);
 

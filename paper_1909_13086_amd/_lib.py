@@ -35,7 +35,7 @@ EXPORTS = (
     "lbm_stream", "lbm_slot_info", "lbm_step_many", "lbm_set_group_bytes",
     "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_set_fusion", "lbm_get_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
-    "lbm_server_request", "lbm_server_summary",
+    "lbm_server_request", "lbm_server_summary", "lbm_server_on_finish",
 )
 
 

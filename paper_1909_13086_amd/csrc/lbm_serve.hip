@@ -192,7 +192,34 @@ struct lbm_server {
   std::vector<Req> reqs;
   bool ran = false;
   lbm_serve_summary summary{};
+  lbm_request_fn on_finish = nullptr;
+  void *user = nullptr;
 };
+
+namespace {
+
+void fill_request(const Req &r, lbm_request *out) {
+  std::memset(out, 0, sizeof(*out));
+  out->id = r.id;
+  out->status = r.status;
+  out->precision = r.cs.precision;
+  out->steps = r.steps;
+  out->cells = r.cells;
+  out->t_arrival = r.t_arr;
+  out->t_admit = r.t_adm;
+  out->t_done = r.t_done;
+  out->bytes = r.bytes;
+  out->stats = r.stats;
+}
+
+void notify(const lbm_server *s, const Req &r) {
+  if (!s->on_finish) return;
+  lbm_request out;
+  fill_request(r, &out);
+  s->on_finish(&out, s->user);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -284,6 +311,7 @@ int lbm_server_run(lbm_server *s, double time_scale) {
         ++sum.rejected;
         ++finished;
         it = pending.erase(it);
+        notify(s, r);
         continue;
       }
       size_t off = 0;
@@ -350,6 +378,7 @@ int lbm_server_run(lbm_server *s, double time_scale) {
       if (r.status == LBM_REQ_DONE) ++sum.completed; else ++sum.failed;
       ++finished;
       it = resident.erase(it);
+      notify(s, r);
     }
   }
   std::vector<double> lat;
@@ -373,21 +402,18 @@ int lbm_server_run(lbm_server *s, double time_scale) {
   return LBM_OK;
 }
 
+int lbm_server_on_finish(lbm_server *s, lbm_request_fn fn, void *user) {
+  if (!s) return sfail(LBM_EINVAL, "server is NULL");
+  if (s->ran) return sfail(LBM_ESTATE, "the loop has already run");
+  s->on_finish = fn;
+  s->user = user;
+  return LBM_OK;
+}
+
 int lbm_server_request(lbm_server *s, int32_t id, lbm_request *out) {
   if (!s || !out) return sfail(LBM_EINVAL, "NULL argument");
   if (id < 0 || id >= (int32_t)s->reqs.size()) return sfail(LBM_EINVAL, "unknown request");
-  const Req &r = s->reqs[id];
-  std::memset(out, 0, sizeof(*out));
-  out->id = r.id;
-  out->status = r.status;
-  out->precision = r.cs.precision;
-  out->steps = r.steps;
-  out->cells = r.cells;
-  out->t_arrival = r.t_arr;
-  out->t_admit = r.t_adm;
-  out->t_done = r.t_done;
-  out->bytes = r.bytes;
-  out->stats = r.stats;
+  fill_request(s->reqs[id], out);
   return LBM_OK;
 }
 

@@ -38,6 +38,8 @@ class lbm_serve_summary(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+REQUEST_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(lbm_request), ctypes.c_void_p)
+
 _sig_done = False
 
 
@@ -59,6 +61,8 @@ def _lib():
         lib.lbm_server_request.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(lbm_request)]
         lib.lbm_server_summary.restype = ctypes.c_int
         lib.lbm_server_summary.argtypes = [vp, ctypes.POINTER(lbm_serve_summary)]
+        lib.lbm_server_on_finish.restype = ctypes.c_int
+        lib.lbm_server_on_finish.argtypes = [vp, REQUEST_FN, vp]
         _sig_done = True
     return lib
 
@@ -80,6 +84,11 @@ class Server:
                                           ctypes.byref(rid)))
         self.n += 1
         return rid.value
+
+    def on_finish(self, fn):
+        """fn(request dict) is called as each request leaves the loop."""
+        self._cb = REQUEST_FN(lambda r, _user: fn(r.contents.as_dict())) if fn else REQUEST_FN()
+        L._check(_lib().lbm_server_on_finish(self.h, self._cb, None))
 
     def run(self, time_scale=1.0):
         L._check(_lib().lbm_server_run(self.h, float(time_scale)))
@@ -109,10 +118,14 @@ class Server:
             pass
 
 
-def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 << 30, chunk=100, seed=5):
+def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 << 30, chunk=100, seed=5,
+                  progress_every=0):
     """Replays a seeded Poisson trace (sizes 256x128 ... 2048x1024, Ra
     log-uniform in [1e6, 1e8], random heater position, FP64 or FP32-shifted
-    at random) through the loop and returns its summary."""
+    at random) through the loop and returns its summary.  With
+    progress_every > 0 a line goes to stderr each time that many requests
+    have finished."""
+    import sys
     from btrirt_workloads import serving_trace
     trace = serving_trace(seed=seed, n=n, rate=rate, steps_lo=steps_lo, steps_hi=steps_hi)
     ctx = P.Context(device=0, max_slots=n, lend_memory=False)
@@ -120,6 +133,15 @@ def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 <<
     srv = Server(ctx.h, budget, chunk)
     for r in trace:
         srv.submit(dict(r["case"], precision=r["precision"]), r["steps"], r["arrival"])
+    if progress_every > 0:
+        done = [0]
+
+        def report(req):
+            done[0] += 1
+            if done[0] % progress_every == 0 or done[0] == n:
+                print(f"[serve] {done[0]}/{n} requests finished, t = {req['t_done']:.1f} s", file=sys.stderr,
+                      flush=True)
+        srv.on_finish(report)
     srv.run(1.0)
     s = srv.summary()
     srv.close()

@@ -122,3 +122,23 @@ def test_invalid_submissions():
     with pytest.raises(P.LbmError):
         serve.Server(None, 1 << 10, 100, fake_mlups=1e4)
     srv.close()
+
+
+def test_finish_callback_reports_every_request_once_in_completion_order():
+    c = cavity(256, 128)
+    reqs = [(c, 300, 0.0), (cavity(2048, 1024), 100, 0.0), (c, 100, 0.01), (cavity(128, 64), 50, 0.02)]
+    srv = serve.Server(None, 4 * aligned(footprint(c)), 100, fake_mlups=2e4)
+    for case, steps, t in reqs:
+        srv.submit(case, steps, t)
+    seen = []
+    srv.on_finish(seen.append)
+    srv.run(1.0)
+    recs = srv.requests()
+    with pytest.raises(P.LbmError):  # the loop has run: no new callback
+        srv.on_finish(None)
+    srv.close()
+    assert sorted(r["id"] for r in seen) == [0, 1, 2, 3]
+    assert [r["t_done"] for r in seen] == sorted(r["t_done"] for r in seen)
+    for r in seen:
+        assert r == recs[r["id"]]
+    assert [r["status"] for r in seen if r["id"] == 1] == [serve.LBM_REQ_REJECTED]
