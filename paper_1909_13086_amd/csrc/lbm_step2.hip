@@ -42,11 +42,29 @@ __device__ constexpr int along_slot(int i) {
   return D > 0 ? (i == 2 ? 0 : (i == 5 ? 1 : 2)) : (i == 4 ? 0 : (i == 7 ? 1 : 2));
 }
 
+// Wavefront-wide lane shifts by one lane (DPP wave_shr:1 / wave_shl:1): a
+// lane receives the value of lane - 1 or lane + 1; the first or last lane,
+// which has no source, keeps its own value.
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v) {
+  const int i = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
+}
+
 template <typename R>
 __device__ __forceinline__ R lane_from(R v, int dx) {
   // value of the lane holding column x - dx
-  if (dx > 0) return __shfl_up(v, 1, kWave);
-  if (dx < 0) return __shfl_down(v, 1, kWave);
+  if (dx > 0) return dpp_shift<kDppWaveShr1>(v);
+  if (dx < 0) return dpp_shift<kDppWaveShl1>(v);
   return v;
 }
 
