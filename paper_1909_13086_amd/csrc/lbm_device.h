@@ -57,6 +57,7 @@ template <typename R>
 struct Coef {
   R k0g, dk1g, dk2g;       // k0, k1 - k0, k2 - k0 for g
   R k0f, dk1f, dk2f;       // same for f
+  R omk0g, omk0f;          // 1 - k0
   R hk1f, hk2f;            // 1 - k1/2, 1 - k2/2 for the force terms
   R Cp, inv_Cp, L, inv_L, rho0, inv_rho0, gb, Tm;
   R c2[3];                 // 2 w_i Cp (Th - Tm) for w = 4/9 (unused), 1/9, 1/36
@@ -68,6 +69,8 @@ struct Coef {
     k0f = R(c.k0f);
     dk1f = R(c.k1f - c.k0f);
     dk2f = R(c.k2f - c.k0f);
+    omk0g = R(1.0 - c.k0g);
+    omk0f = R(1.0 - c.k0f);
     hk1f = R(1.0 - 0.5 * c.k1f);
     hk2f = R(1.0 - 0.5 * c.k2f);
     Cp = R(c.Cp);
@@ -100,25 +103,53 @@ __device__ __forceinline__ void enthalpy_map(R dH, R L, R inv_L, R inv_Cp, R &fl
   th = solid ? dH * inv_Cp : (liquid ? (dH - L) * inv_Cp : R(0));
 }
 
-// Relaxation of Eq. (2) written with the combined first- and second-moment
-// corrections a1, a2:  p_i <- p_i - k0 (p_i - peq_i) - 3 w_i c_i.a1
-//                              - (9/2) w_i (c_i c_i - I/3):a2.
+// Relaxation of Eq. (2) for a pair of opposite populations (i, opp(i)).
+// With the combined first- and second-moment corrections a1, a2, Eq. (2)
+// reads p_i* = p_i - k0 (p_i - peq_i) - 3 w_i c_i.a1 - (9/2) w_i Q_i:a2,
+// Q_i = c_i c_i - I/3.  Under c -> -c the equilibrium splits into an even
+// part E and an odd part O, c.a1 changes sign and Q:a2 does not, so
+//   p_{+/-}* = (1 - k0) p_{+/-} + (k0 E - t2) +/- (k0 O - t1)
+// with t1 = 3 w c.a1 and t2 = (9/2) w Q:a2 taken for the "+" member.
 template <typename R>
-__device__ __forceinline__ R relax_one(int i, R p, R peq, R k0, R a1x, R a1y, R a2xx, R a2xy,
-                                       R a2yy) {
-  constexpr R third = R(1.0 / 3.0);
-  const R w = R(wgt(i));
-  const R ex = R(cx(i)), ey = R(cy(i));
-  const R c1 = ex * a1x + ey * a1y;
-  const R qa = (ex * ex - third) * a2xx + R(2) * ex * ey * a2xy + (ey * ey - third) * a2yy;
-  return p - k0 * (p - peq) - R(3) * w * c1 - R(4.5) * w * qa;
+__device__ __forceinline__ void relax_pair(R &pp, R &pm, R omk0, R k0, R E, R O, R t1, R t2) {
+  const R even = k0 * E - t2;
+  const R odd = k0 * O - t1;
+  pp = omk0 * pp + (even + odd);
+  pm = omk0 * pm + (even - odd);
 }
 
-// One B-TriRT collision of a cell, shifted populations in place.  Returns
-// nothing; fl/theta/ux/uy are the pre-collision macroscopic values.
+// The four pairs of D2Q9 directions, "+" member first: (1, 3) along x,
+// (2, 4) along y, (5, 7) along (1, 1), (6, 8) along (-1, 1).  For each pair,
+// c.u, c.a1 and Q:a2 of the "+" member.
+template <typename R>
+struct PairTerms {
+  R cu[4], c1[4], qa[4];
+  __device__ PairTerms(R ux, R uy, R a1x, R a1y, R a2xx, R a2xy, R a2yy) {
+    constexpr R third = R(1.0 / 3.0), two_thirds = R(2.0 / 3.0);
+    cu[0] = ux;
+    cu[1] = uy;
+    cu[2] = ux + uy;
+    cu[3] = uy - ux;
+    c1[0] = a1x;
+    c1[1] = a1y;
+    c1[2] = a1x + a1y;
+    c1[3] = a1y - a1x;
+    const R d = two_thirds * (a2xx + a2yy);
+    qa[0] = two_thirds * a2xx - third * a2yy;
+    qa[1] = two_thirds * a2yy - third * a2xx;
+    qa[2] = d + R(2) * a2xy;
+    qa[3] = d - R(2) * a2xy;
+  }
+};
+__device__ constexpr int pair_plus(int p) { return p == 0 ? 1 : (p == 1 ? 2 : (p == 2 ? 5 : 6)); }
+__device__ constexpr int pair_minus(int p) { return p == 0 ? 3 : (p == 1 ? 4 : (p == 2 ? 7 : 8)); }
+__device__ constexpr double pair_w(int p) { return p < 2 ? 1.0 / 9.0 : 1.0 / 36.0; }
+
+// One B-TriRT collision of a cell, shifted populations in place.
 template <typename R>
 __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]) {
   constexpr R third = R(1.0 / 3.0);
+  constexpr R w0 = R(4.0 / 9.0);
   // (a) total enthalpy
   const R dH = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   // (b) temperature and liquid fraction
@@ -148,11 +179,19 @@ __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]
     const R a2xy = k.dk2f * m2xy - k.hk2f * (ux * Fy);
     const R a2yy = k.dk2f * m2yy - k.hk2f * (R(2) * uy * Fy);
     const R uu15 = R(1.5) * (ux * ux + uy * uy);
+    {
+      const R feq0 = w0 * (drho - k.rho0 * uu15);
+      const R qa0 = -(a2xx + a2yy) * third;
+      f[0] = k.omk0f * f[0] + (k.k0f * feq0 - R(4.5) * w0 * qa0);
+    }
+    const PairTerms<R> t(ux, uy, a1x, a1y, a2xx, a2xy, a2yy);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const R cu = R(cx(i)) * ux + R(cy(i)) * uy;
-      const R feq = R(wgt(i)) * (drho + k.rho0 * (R(3) * cu + R(4.5) * cu * cu - uu15));
-      f[i] = relax_one<R>(i, f[i], feq, k.k0f, a1x, a1y, a2xx, a2xy, a2yy);
+    for (int p = 0; p < 4; ++p) {
+      const R w = R(pair_w(p));
+      const R E = w * (drho + k.rho0 * (R(4.5) * t.cu[p] * t.cu[p] - uu15));
+      const R O = R(3) * w * k.rho0 * t.cu[p];
+      relax_pair<R>(f[pair_plus(p)], f[pair_minus(p)], k.omk0f, k.k0f, E, O, R(3) * w * t.c1[p],
+                    R(4.5) * w * t.qa[p]);
     }
   }
   // (e) enthalpy collision with the equilibrium of Eq. (3)
@@ -171,16 +210,19 @@ __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]
     const R a2xx = k.dk2g * (qxx - Cpth * third);
     const R a2xy = k.dk2g * qxy;
     const R a2yy = k.dk2g * (qyy - Cpth * third);
+    {
+      const R geq0 = dH - Cpth + w0 * Cpth;
+      const R qa0 = -(a2xx + a2yy) * third;
+      g[0] = k.omk0g * g[0] + (k.k0g * geq0 - R(4.5) * w0 * qa0);
+    }
+    const PairTerms<R> t(ux, uy, a1x, a1y, a2xx, a2xy, a2yy);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      R geq;
-      if (i == 0) {
-        geq = dH - Cpth + R(wgt(0)) * Cpth;
-      } else {
-        const R cu = R(cx(i)) * ux + R(cy(i)) * uy;
-        geq = R(wgt(i)) * Cpth + R(3) * R(wgt(i)) * CpT * cu;
-      }
-      g[i] = relax_one<R>(i, g[i], geq, k.k0g, a1x, a1y, a2xx, a2xy, a2yy);
+    for (int p = 0; p < 4; ++p) {
+      const R w = R(pair_w(p));
+      const R E = w * Cpth;
+      const R O = R(3) * w * CpT * t.cu[p];
+      relax_pair<R>(g[pair_plus(p)], g[pair_minus(p)], k.omk0g, k.k0g, E, O, R(3) * w * t.c1[p],
+                    R(4.5) * w * t.qa[p]);
     }
   }
 }
