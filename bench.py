@@ -211,13 +211,15 @@ def two_step_variant(P, steps=400):
     return out
 
 
-def batched_variant(P, steps, chunk=100):
-    """64 cavities of uneven size (seeded sweep), FP32 shifted: one batched
-    launch per step replayed from captured 100-step graphs, against the same
-    cavities solved one after another with the single-cavity path."""
+def batched_variant(P, steps, chunk=100, pattern=None):
+    """64 cavities of uneven size (seeded sweep), FP32 shifted: batched
+    launches replayed from captured 100-step graphs (in place: one launch per
+    step; two lattices: one launch per two steps), against the same cavities
+    solved one after another with the single-cavity path."""
     import torch
     from btrirt_workloads import batch_sweep
-    cases = [dict(c, precision=P.LBM_FP32_SHIFTED) for c in batch_sweep()]
+    pattern = P.LBM_PATTERN_AA if pattern is None else pattern
+    cases = [dict(c, precision=P.LBM_FP32_SHIFTED, pattern=pattern) for c in batch_sweep()]
     cells = sum(c["nx"] * c["ny"] for c in cases)
     ctx = P.Context(device=0, max_slots=len(cases))
     ctx.set_graph_chunk(chunk)
@@ -241,6 +243,7 @@ def batched_variant(P, steps, chunk=100):
     ctx.close()
     lu = cells * steps
     res = dict(cavities=len(cases), cells=cells, steps=steps,
+               pattern="in place" if pattern == P.LBM_PATTERN_AA else "two lattices, two steps per launch",
                batched_mlups=round(lu / (ms_b * 1e-3) / 1e6, 1),
                sequential_mlups=round(lu / (ms_s * 1e-3) / 1e6, 1))
     res["speedup"] = round(res["batched_mlups"] / res["sequential_mlups"], 3)
@@ -350,7 +353,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
-    ap.add_argument("--only", choices=["fp32", "batched", "serving", "serving_study", "two_step"], default="",
+    ap.add_argument("--only", choices=["fp32", "batched", "batched_two_step", "serving", "serving_study", "two_step"],
+                    default="",
                     help="run one variant alone (for profiling) and print its result")
     ap.add_argument("--study", choices=["heater"], default="",
                     help="run the heater-position study of the cavity section instead of the benchmark")
@@ -376,6 +380,8 @@ def main():
             res = fp32_variant(P, max(500, args.steps // 4), args.path)
         elif args.only == "batched":
             res = batched_variant(P, args.steps)
+        elif args.only == "batched_two_step":
+            res = batched_variant(P, args.steps, pattern=P.LBM_PATTERN_AB)
         elif args.only == "two_step":
             res = two_step_variant(P, args.steps)
         elif args.only == "serving_study":
@@ -420,6 +426,7 @@ def main():
         out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4), path)
         out["hbm_bound_4096x2048"] = hbm_bound_variant(P)
         out["batched"] = batched_variant(P, 2000)
+        out["batched_two_step"] = batched_variant(P, 2000, pattern=P.LBM_PATTERN_AB)
         try:
             from paper_1909_13086_amd import serve
             out["serving"] = serve.bench_serving(P)

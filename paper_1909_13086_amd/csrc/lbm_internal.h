@@ -91,6 +91,15 @@ hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hi
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
                              const int32_t *hdr_dev, int tile_cap, int precision, int tile_bx,
                              int tile_rows, int launch_index, int grid, hipStream_t s);
+// Batched two-step launch over wavefront items {cavity, strip origin x0,
+// segment origin y0, segment index} of two-lattice cavities: launch j
+// advances cavity c by two steps while 2 j + 2 <= active_steps(c), by one
+// step when 2 j + 1 == active_steps(c), else leaves it.
+hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
+                              const int32_t *hdr_dev, int item_cap, int precision,
+                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s);
+// Workgroups of a batched two-step launch that fill the device once.
+int step2_batch_grid(int num_cus);
 hipError_t launch_reduce(const CavDev &c, int precision, double *partials, StatsDev *out,
                          hipStream_t s);
 hipError_t launch_fields(const CavDev &c, int precision, uint32_t mask, double *out,

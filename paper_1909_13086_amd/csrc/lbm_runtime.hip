@@ -196,7 +196,9 @@ struct Batch {
   BatchTile *tiles_host = nullptr;
   int32_t *hdr_host = nullptr;
   std::vector<int> members;       // slot ids in cavity-array order
-  std::vector<int> group_precs;   // per group: bit p set when it holds precision p
+  std::vector<int> group_precs;   // per group: bit 2 p + kind set when it holds such launches
+                                  // (kind 0: one step per launch over tiles, kind 1: two-step
+                                  // launches over strip segments)
   bool dirty = true;
   hipGraphExec_t graph = nullptr; // valid while the device buffers and the group shape stay
   int graph_chunk = 0;
@@ -465,6 +467,10 @@ namespace {
 
 constexpr int kBatchTileX = 64;
 constexpr int kBatchTileRows = 16;
+constexpr int kStrip2Cols = lbm::kWave - 2;  // owned columns of a two-step wavefront
+
+// Header slot of (cache group, precision, kind) in the batch header array.
+int hdr_index(int g, int prec, int kind) { return ((g * 2 + prec) * 2 + kind) * 2; }
 
 void free_batch(lbm_ctx *c) {
   Batch &b = c->batch;
@@ -507,19 +513,25 @@ int rebuild_batch(lbm_ctx *c) {
     group_of[j] = ngroups - 1;
   }
   const size_t ncav = b.members.size();
+  // work items: 64 x 16 tiles for one-step cavities, strip segments
+  // (62 columns x seg rows, one wavefront each) for two-step cavities
+  auto items_of = [&](const Slot &s) -> size_t {
+    if (fused(c, s)) {
+      const int seg = c->launch[s.cs.precision].seg;
+      return (size_t)((s.cs.nx + kStrip2Cols - 1) / kStrip2Cols) * ((s.cs.ny + seg - 1) / seg);
+    }
+    return (size_t)((s.cs.nx + kBatchTileX - 1) / kBatchTileX) *
+           ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
+  };
   size_t ntiles = 0;
-  for (int id : b.members) {
-    const Slot &s = c->slots[id];
-    ntiles += (size_t)((s.cs.nx + kBatchTileX - 1) / kBatchTileX) *
-              ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
-  }
-  const size_t nhdr = (size_t)std::max(ngroups, 1) * 4;
+  for (int id : b.members) ntiles += items_of(c->slots[id]);
+  const size_t nhdr = (size_t)std::max(ngroups, 1) * 8;
   HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
   if (ncav > b.cav_cap || ntiles > b.tile_cap || nhdr > b.hdr_cap) {
     free_batch(c);
     b.cav_cap = std::max<size_t>(ncav, c->slots.size());
     b.tile_cap = std::max<size_t>(ntiles * 2, 4096);
-    b.hdr_cap = std::max<size_t>(nhdr * 2, 4 * 64);
+    b.hdr_cap = std::max<size_t>(nhdr * 2, 8 * 64);
     HIP_TRY(hipMalloc(&b.cavs_dev, b.cav_cap * sizeof(CavDev)));
     HIP_TRY(hipMalloc(&b.tiles_dev, b.tile_cap * sizeof(BatchTile)));
     HIP_TRY(hipMalloc(&b.hdr_dev, b.hdr_cap * sizeof(int32_t)));
@@ -532,25 +544,35 @@ int rebuild_batch(lbm_ctx *c) {
   size_t t = 0;
   for (int g = 0; g < ngroups; ++g) {
     for (int prec = 0; prec < 2; ++prec) {
-      const size_t first = t;
-      for (size_t j = 0; j < ncav; ++j) {
-        if (group_of[j] != g) continue;
-        const Slot &s = c->slots[b.members[j]];
-        if (s.cs.precision != prec) continue;
-        for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
-          for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
-            b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
+      for (int kind = 0; kind < 2; ++kind) {
+        const size_t first = t;
+        for (size_t j = 0; j < ncav; ++j) {
+          if (group_of[j] != g) continue;
+          const Slot &s = c->slots[b.members[j]];
+          if (s.cs.precision != prec || (int)fused(c, s) != kind) continue;
+          if (kind == 0) {
+            for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
+              for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
+                b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
+          } else {
+            const int seg = c->launch[prec].seg;
+            for (int y0 = 0, k = 0; y0 < s.cs.ny; y0 += seg, ++k)
+              for (int x0 = 0; x0 < s.cs.nx; x0 += kStrip2Cols)
+                b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, k};
+          }
+        }
+        const int h = hdr_index(g, prec, kind);
+        b.hdr_host[h] = (int32_t)first;
+        b.hdr_host[h + 1] = (int32_t)(t - first);
+        if (t > first) b.group_precs[g] |= 1 << (prec * 2 + kind);
       }
-      b.hdr_host[(g * 2 + prec) * 2] = (int32_t)first;
-      b.hdr_host[(g * 2 + prec) * 2 + 1] = (int32_t)(t - first);
-      if (t > first) b.group_precs[g] |= 1 << prec;
     }
   }
   if (t > 0)
     HIP_TRY(hipMemcpyAsync(b.tiles_dev, b.tiles_host, t * sizeof(BatchTile),
                            hipMemcpyHostToDevice, c->stream));
   if (ngroups > 0)
-    HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host, (size_t)ngroups * 4 * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host, (size_t)ngroups * 8 * sizeof(int32_t),
                            hipMemcpyHostToDevice, c->stream));
   b.dirty = false;
   return LBM_OK;
@@ -558,16 +580,25 @@ int rebuild_batch(lbm_ctx *c) {
 
 int batch_grid(lbm_ctx *c) { return c->num_cus * 8; }
 
+// Launches of one chunk: per cache group, `chunk` one-step launches and
+// ceil(chunk / 2) two-step launches for each precision present.
 hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
   Batch &b = c->batch;
   hipError_t err = hipSuccess;
-  for (int g = 0; g < (int)b.group_precs.size() && err == hipSuccess; ++g)
+  for (int g = 0; g < (int)b.group_precs.size() && err == hipSuccess; ++g) {
     for (int k = 0; k < chunk && err == hipSuccess; ++k)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-        if (b.group_precs[g] & (1 << prec))
-          err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + (g * 2 + prec) * 2,
+        if (b.group_precs[g] & (1 << (prec * 2)))
+          err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + hdr_index(g, prec, 0),
                                        (int)b.tile_cap, prec, kBatchTileX, kBatchTileRows, k,
                                        batch_grid(c), c->stream);
+    for (int j = 0; j < (chunk + 1) / 2 && err == hipSuccess; ++j)
+      for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
+        if (b.group_precs[g] & (1 << (prec * 2 + 1)))
+          err = lbm::launch_step2_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + hdr_index(g, prec, 1),
+                                        (int)b.tile_cap, prec, c->launch[prec], j,
+                                        lbm::step2_batch_grid(c->num_cus), c->stream);
+  }
   return err;
 }
 
@@ -639,7 +670,9 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
       Slot &s = c->slots[id];
       const int64_t adv = std::min<int64_t>(left[id], chunk);
       s.step += adv;
-      if (adv & 1) s.dev.parity ^= 1;
+      // one parity flip per launch that advanced the slot
+      const int64_t launches = fused(c, s) ? (adv + 1) / 2 : adv;
+      if (launches & 1) s.dev.parity ^= 1;
       left[id] -= adv;
     }
     most -= chunk;
@@ -988,6 +1021,7 @@ int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags
   L.zigzag = (flags & LBM_LAUNCH_ZIGZAG) ? 1 : 0;
   L.staged = (flags & LBM_LAUNCH_STAGED) ? 1 : 0;
   for (auto &s : c->slots) drop_graphs(s);
+  drop_batch_graph(c);
   return LBM_OK;
 }
 
@@ -1013,6 +1047,8 @@ int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_
   c->launch[precision].fuse = steps_per_launch;
   c->launch[precision].seg = segment_rows;
   for (auto &s : c->slots) drop_graphs(s);
+  c->batch.dirty = true;  // item lists depend on the fusion
+  drop_batch_graph(c);
   return LBM_OK;
 }
 

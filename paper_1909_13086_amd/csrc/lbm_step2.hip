@@ -412,7 +412,99 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Batched two-step launch: each wavefront takes items (one strip segment of
+// one cavity) from its XCD's contiguous band of the item list, so the
+// segments of a cavity share that XCD's L2.  Cavity state comes from the
+// device array, so a captured launch stays valid when cavities join or
+// leave.  The storage parity in launch j is the chunk-start parity flipped j
+// times: every earlier launch of the chunk advanced the cavity.
+template <typename S, typename R, bool STAGED>
+__global__ __launch_bounds__(STAGED ? kStagedWaves * kWave : kDirectWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restrict__ cavs,
+                                                           const BatchTile *__restrict__ items,
+                                                           const int32_t *__restrict__ hdr,
+                                                           int item_cap, int seg_rows,
+                                                           int launch_index, int order) {
+  constexpr int waves = STAGED ? kStagedWaves : kDirectWaves;
+  __shared__ S lds[STAGED ? waves * 2 * kPlanes * kWave : 1];
+  const int first = hdr[0], n = hdr[1];
+  if (first < 0 || n <= 0 || first > item_cap - n) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
+  const int nbx = (gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int t0 = (int)((int64_t)n * xcd / kXcds);
+  const int t1 = (int)((int64_t)n * (xcd + 1) / kXcds);
+  for (int t = t0 + lb * waves + wid; t < t1; t += nbx * waves) {  // uniform per wavefront
+    const BatchTile it = items[first + t];
+    CavDev c = cavs[it.cav];
+    const int a = c.active_steps;
+    if (2 * launch_index + 1 > a) continue;
+    c.parity ^= (launch_index & 1);
+    const int y0 = it.y0;
+    const int y1 = min(y0 + seg_rows, c.ny);
+    const Coef<R> k(c);
+    const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
+    S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
+    if (2 * launch_index + 2 <= a) {
+      const Col q = make_col(c, it.x0 - 1 + lane, lane, y0);
+      const bool down = (order & 4) && (it.pad & 1);
+      if constexpr (STAGED) {
+        S *bufs = lds + wid * 2 * kPlanes * kWave;
+        if (down)
+          walk_staged<S, R, -1>(c, k, A, B, q, y0, y1, it.x0, bufs);
+        else
+          walk_staged<S, R, +1>(c, k, A, B, q, y0, y1, it.x0, bufs);
+      } else {
+        if (down)
+          walk_direct<S, R, -1>(c, k, A, B, q, y0, y1);
+        else
+          walk_direct<S, R, +1>(c, k, A, B, q, y0, y1);
+      }
+    } else {
+      // the odd last step of the chunk: single two-lattice steps of the
+      // segment's owned cells
+      const int x = it.x0 - 1 + lane;
+      if (lane >= 1 && lane <= kStripCols && x < c.nx)
+        for (int y = y0; y < y1; ++y) update_cell<S, R>(c, k, 2, x, y);
+    }
+  }
+}
+
+template <typename S, typename R, bool STAGED>
+hipError_t dispatch_batch(const CavDev *cavs, const BatchTile *items, const int32_t *hdr,
+                          int item_cap, const LaunchCfg &cfg, int launch_index, int grid,
+                          hipStream_t s) {
+  if (cfg.seg < 1 || cfg.seg > kMaxSegmentRows) return hipErrorInvalidValue;
+  const int per_block = STAGED ? kStagedWaves : kDirectWaves;
+  const int order = cfg.zigzag ? 4 : 0;
+  hipLaunchKernelGGL((k_step2_batch<S, R, STAGED>), dim3(grid), dim3(per_block * kWave), 0, s,
+                     cavs, items, hdr, item_cap, cfg.seg, launch_index, order);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int step2_batch_grid(int num_cus) {
+  // four 2-wavefront workgroups (or two 4-wavefront ones) per CU
+  return num_cus * 4;
+}
+
+hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
+                              const int32_t *hdr_dev, int item_cap, int precision,
+                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
+  if (cfg.staged)
+    return precision == 0
+               ? dispatch_batch<double, double, true>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
+                                                      launch_index, grid, s)
+               : dispatch_batch<float, float, true>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
+                                                    launch_index, grid, s);
+  return precision == 0
+             ? dispatch_batch<double, double, false>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
+                                                     launch_index, grid, s)
+             : dispatch_batch<float, float, false>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
+                                                   launch_index, grid, s);
+}
 
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {
   if (cfg.staged)

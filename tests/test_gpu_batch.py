@@ -88,3 +88,51 @@ def test_batch_sweep_generator_shapes():
     cav = batch_sweep()
     assert len(cav) == 64
     assert all(256 <= c["nx"] <= 1024 and c["nx"] % 64 == 0 and c["ny"] == c["nx"] // 2 for c in cav)
+
+
+def _ab_cases(P):
+    return [
+        dict(cavity(200, 50, Ra=1e6, heater_center=0.4), precision=P.LBM_FP64, pattern=P.LBM_PATTERN_AB),
+        dict(cavity(130, 40, periodic_x=1, Ra=3e6, heater_center=0.6), precision=P.LBM_FP32_SHIFTED,
+             pattern=P.LBM_PATTERN_AB),
+        dict(cavity(96, 33, periodic_x=1, periodic_y=1, Ra=1e5), precision=P.LBM_FP64,
+             pattern=P.LBM_PATTERN_AB),
+        dict(cavity(150, 64, Ra=1e7, heater_center=0.5), precision=P.LBM_FP64),
+    ]
+
+
+@pytest.mark.parametrize("flags,seg", [(None, None), (13, 5), (21, 3), (29, 1)])
+def test_two_step_batch_uneven_steps_equal_solo(P, flags, seg):
+    """Two-lattice cavities advance two steps per batched launch (one step for
+    an odd remainder), next to an in-place cavity, with per-slot step counts,
+    graph chunks and every launch mode of the two-step kernel."""
+    print(f"case two-step batch flags={flags} seg={seg}", flush=True)
+    cases = _ab_cases(P)
+    states = [_random_state(70 + k, c["nx"], c["ny"]) for k, c in enumerate(cases)]
+    counts = [7, 12, 1, 9]
+    with P.Context(device=0, max_slots=8) as ctx:
+        for prec in (0, 1):
+            if flags is not None:
+                ctx.set_launch(prec, 256, 1, 1, flags)
+            if seg is not None:
+                ctx.set_fusion(prec, 2, seg)
+        ctx.set_graph_chunk(4)
+        slots = []
+        for c, (f0, g0) in zip(cases, states):
+            s = ctx.add(c)
+            ctx.state_load(s, f0, g0)
+            slots.append(s)
+        ctx.step_many(slots, counts)
+        ctx.step(P.LBM_ALL, 10)
+        got = [(ctx.state_save(s), ctx.reduce(s)) for s in slots]
+    for k, c in enumerate(cases):
+        n = counts[k] + 10
+        with P.Context(device=0, max_slots=1) as ctx:
+            s = ctx.add(c)
+            ctx.state_load(s, *states[k])
+            ctx.step(s, n)
+            want = (ctx.state_save(s), ctx.reduce(s))
+        assert got[k][1]["step"] == n
+        assert np.array_equal(got[k][0][0], want[0][0]) and np.array_equal(got[k][0][1], want[0][1]), k
+        for key in ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "budget_residual"):
+            assert got[k][1][key] == want[1][key], (k, key)
