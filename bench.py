@@ -251,7 +251,7 @@ def batched_variant(P, steps, chunk=100, pattern=None):
     return res
 
 
-def serving_study(P):
+def serving_study(P, pattern):
     """The full serving workload (256 seeded Poisson requests at 20/s, sizes
     256x128 ... 2048x1024, 1000-50000 steps, FP64 / FP32-shifted 50/50, 16 GB
     budget), whose offered load is far above the device's, then the first 64
@@ -259,13 +259,13 @@ def serving_study(P):
     throughput the full run sustained."""
     from paper_1909_13086_amd import serve
     from btrirt_workloads import serving_trace
-    full = serve.bench_serving(P, n=256, steps_hi=50000, progress_every=16)
+    full = serve.bench_serving(P, n=256, steps_hi=50000, progress_every=16, pattern=pattern)
     log(f"serving, full trace: {full}")
     n70 = 64
     tr = serving_trace(seed=5, n=n70, steps_hi=50000)
     mean_lu = sum(r["case"]["nx"] * r["case"]["ny"] * r["steps"] for r in tr) / n70
     rate = 0.7 * full["mlups"] * 1e6 / mean_lu
-    at70 = serve.bench_serving(P, n=n70, rate=rate, steps_hi=50000, progress_every=8)
+    at70 = serve.bench_serving(P, n=n70, rate=rate, steps_hi=50000, progress_every=8, pattern=pattern)
     at70["offered_mlups"] = round(rate * mean_lu / 1e6, 1)
     log(f"serving at 70 % of capacity: {at70}")
     return dict(full=full, at_70_percent=at70)
@@ -353,7 +353,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
-    ap.add_argument("--only", choices=["fp32", "batched", "batched_two_step", "serving", "serving_study", "two_step"],
+    ap.add_argument("--only", choices=["fp32", "batched", "batched_two_step", "serving", "serving_two_step",
+                                       "serving_study", "two_step"],
                     default="",
                     help="run one variant alone (for profiling) and print its result")
     ap.add_argument("--study", choices=["heater"], default="",
@@ -385,7 +386,10 @@ def main():
         elif args.only == "two_step":
             res = two_step_variant(P, args.steps)
         elif args.only == "serving_study":
-            res = serving_study(P)
+            res = serving_study(P, P.LBM_PATTERN_AB if args.path == "ab2" else P.LBM_PATTERN_AA)
+        elif args.only == "serving_two_step":
+            from paper_1909_13086_amd import serve
+            res = serve.bench_serving(P, pattern=P.LBM_PATTERN_AB)
         else:
             from paper_1909_13086_amd import serve
             res = serve.bench_serving(P)
@@ -427,11 +431,9 @@ def main():
         out["hbm_bound_4096x2048"] = hbm_bound_variant(P)
         out["batched"] = batched_variant(P, 2000)
         out["batched_two_step"] = batched_variant(P, 2000, pattern=P.LBM_PATTERN_AB)
-        try:
-            from paper_1909_13086_amd import serve
-            out["serving"] = serve.bench_serving(P)
-        except ImportError:
-            pass
+        from paper_1909_13086_amd import serve
+        out["serving"] = serve.bench_serving(P)
+        out["serving_two_step"] = serve.bench_serving(P, pattern=P.LBM_PATTERN_AB)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

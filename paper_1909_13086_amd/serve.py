@@ -119,10 +119,11 @@ class Server:
 
 
 def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 << 30, chunk=100, seed=5,
-                  progress_every=0):
+                  progress_every=0, pattern=None):
     """Replays a seeded Poisson trace (sizes 256x128 ... 2048x1024, Ra
     log-uniform in [1e6, 1e8], random heater position, FP64 or FP32-shifted
-    at random) through the loop and returns its summary.  With
+    at random) through the loop and returns its summary.  pattern (None:
+    in place) sets every request's streaming pattern.  With
     progress_every > 0 a line goes to stderr each time that many requests
     have finished."""
     import sys
@@ -131,8 +132,9 @@ def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 <<
     ctx = P.Context(device=0, max_slots=n, lend_memory=False)
     ctx.set_graph_chunk(chunk)
     srv = Server(ctx.h, budget, chunk)
+    pattern = P.LBM_PATTERN_AA if pattern is None else pattern
     for r in trace:
-        srv.submit(dict(r["case"], precision=r["precision"]), r["steps"], r["arrival"])
+        srv.submit(dict(r["case"], precision=r["precision"], pattern=pattern), r["steps"], r["arrival"])
     if progress_every > 0:
         done = [0]
 
@@ -147,6 +149,7 @@ def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 <<
     srv.close()
     ctx.close()
     out = dict(requests=n, arrival_rate_per_s=rate, steps_range=[steps_lo, steps_hi], budget_bytes=budget,
+               pattern="in place" if pattern == P.LBM_PATTERN_AA else "two lattices, two steps per launch",
                p50_s=round(s["p50_s"], 4), p99_s=round(s["p99_s"], 4), mean_s=round(s["mean_s"], 4),
                mlups=round(s["mlups"], 1), makespan_s=round(s["makespan_s"], 3),
                busy_frac=round(s["busy_frac"], 4), max_resident=s["max_resident"],
