@@ -120,8 +120,10 @@ __device__ __forceinline__ void zero_row(R (&f)[kQ], R (&g)[kQ]) {
 }
 
 // Second step of row y: the streamed state gathered from the window, walls
-// applied, then collided (result in pf, pg).
-template <typename R, int D>
+// applied (WALLS = false: the wavefront's cells and their neighbours are all
+// inside the cavity, no link crosses a wall), then collided (result in pf,
+// pg).
+template <typename R, int D, bool WALLS = true>
 __device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k, const Col &q, int y,
                                                const R (&cf)[kQ], const R (&cg)[kQ],
                                                const R (&nf)[kQ], const R (&ng)[kQ],
@@ -150,7 +152,7 @@ __device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k
     vg = lane_from(vg, ex);
     const bool in_x = ex > 0 ? xm_in : (ex < 0 ? xp_in : true);
     const bool in_y = ey > 0 ? ym_in : (ey < 0 ? yp_in : true);
-    if (!(in_x && in_y)) {
+    if (WALLS && !(in_x && in_y)) {
       // the link crossed a wall: it comes back from the cell itself
       vf = cf[opp(i)];
       vg = cg[opp(i)];
@@ -162,14 +164,49 @@ __device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k
   collide<R>(k, pf, pg);
 }
 
-// Stores of an owned cell's second step (and its strip flux).
+// Post-collision populations of an interior cell pushed to its neighbours'
+// natural slots: three row bases (wavefront-uniform) and three column
+// offsets within a row, so every address is a row pointer plus a 32-bit
+// offset.
 template <typename S, typename R>
+__device__ __forceinline__ void store_interior(const CavDev &c, S *__restrict__ B, int x, int y,
+                                               const R (&f)[kQ], const R (&g)[kQ]) {
+  const int64_t row_elems = (int64_t)(c.pitch >> 6) * (kPlanes * kWave);
+  S *rows[3];
+  uint32_t cols[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rows[d] = B + (int64_t)(y - 1 + d) * row_elems;
+    const int xx = x - 1 + d;
+    cols[d] = (uint32_t)((xx >> 6) * (kPlanes * kWave) + (xx & (kWave - 1)));
+  }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    S *r = rows[cy(i) + 1];
+    const uint32_t o = cols[cx(i) + 1] + (uint32_t)(i * kWave);
+    r[o] = S(f[i]);
+    r[o + kQ * kWave] = S(g[i]);
+  }
+}
+
+// Stores of an owned cell's second step (and its strip flux).
+template <typename S, typename R, bool WALLS = true>
 __device__ __forceinline__ void emit(const CavDev &c, const Coef<R> &k, S *__restrict__ B, const Col &q,
                                      int y, const R (&pf)[kQ], const R (&pg)[kQ]) {
   if (q.owner) {
-    store_scatter<S, R>(c, k, B, q.x, y, cell_base(c, q.x, y), pf, pg);
-    if (q.bottom_hot && y == 0) add_strip_flux<R>(c, k, q.x, pg);
+    if constexpr (WALLS) {
+      store_scatter<S, R>(c, k, B, q.x, y, cell_base(c, q.x, y), pf, pg);
+      if (q.bottom_hot && y == 0) add_strip_flux<R>(c, k, q.x, pg);
+    } else {
+      store_interior<S, R>(c, B, q.x, y, pf, pg);
+    }
   }
+}
+
+// No cell of the strip segment [x0, x0 + 62) x [y0, y1) or of its neighbours
+// lies on or beyond a wall or a periodic seam.
+__device__ __forceinline__ bool interior_segment(const CavDev &c, int x0, int y0, int y1) {
+  return x0 >= 1 && x0 + kStripCols + 1 <= c.nx && y0 >= 1 && y1 + 1 <= c.ny;
 }
 
 // Window slide: (a, c) <- (populations of c moving along D, n).
@@ -315,7 +352,7 @@ __device__ __forceinline__ void read_row(const S *buf, int lane, R (&f)[kQ], R (
 // copy of row k + 1 is issued into the buffer that row k - 1 has left, before
 // row k is read and collided; it is waited for before the stores of that
 // iteration are issued, so the stores never delay a later wait.
-template <typename S, typename R, int D>
+template <typename S, typename R, int D, bool WALLS>
 __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
                                             S *__restrict__ B, const Col &q, int y0, int y1, int x0,
                                             S *bufs) {
@@ -355,9 +392,9 @@ __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, c
     if (y + D != ye) issue(y + 2 * D, b ^ 1);
     first_step(y + D, b, nf, ng);
     R pf[kQ], pg[kQ];
-    second_collide<R, D>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
+    second_collide<R, D, WALLS>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
     wait_vm();
-    emit<S, R>(c, k, B, q, y, pf, pg);
+    emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
     slide<D>(af, ag, cf, cg, nf, ng);
   }
 }
@@ -386,10 +423,18 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
   const bool down = (order & 4) && (seg & 1);
   if constexpr (STAGED) {
     S *bufs = lds + wid * 2 * kPlanes * kWave;
-    if (down)
-      walk_staged<S, R, -1>(c, k, A, B, q, y0, y1, x0, bufs);
-    else
-      walk_staged<S, R, +1>(c, k, A, B, q, y0, y1, x0, bufs);
+    const bool inner = interior_segment(c, x0, y0, y1);
+    if (down) {
+      if (inner)
+        walk_staged<S, R, -1, false>(c, k, A, B, q, y0, y1, x0, bufs);
+      else
+        walk_staged<S, R, -1, true>(c, k, A, B, q, y0, y1, x0, bufs);
+    } else {
+      if (inner)
+        walk_staged<S, R, +1, false>(c, k, A, B, q, y0, y1, x0, bufs);
+      else
+        walk_staged<S, R, +1, true>(c, k, A, B, q, y0, y1, x0, bufs);
+    }
   } else {
     if (down)
       walk_direct<S, R, -1>(c, k, A, B, q, y0, y1);
@@ -451,10 +496,18 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restr
       const bool down = (order & 4) && (it.pad & 1);
       if constexpr (STAGED) {
         S *bufs = lds + wid * 2 * kPlanes * kWave;
-        if (down)
-          walk_staged<S, R, -1>(c, k, A, B, q, y0, y1, it.x0, bufs);
-        else
-          walk_staged<S, R, +1>(c, k, A, B, q, y0, y1, it.x0, bufs);
+        const bool inner = interior_segment(c, it.x0, y0, y1);
+        if (down) {
+          if (inner)
+            walk_staged<S, R, -1, false>(c, k, A, B, q, y0, y1, it.x0, bufs);
+          else
+            walk_staged<S, R, -1, true>(c, k, A, B, q, y0, y1, it.x0, bufs);
+        } else {
+          if (inner)
+            walk_staged<S, R, +1, false>(c, k, A, B, q, y0, y1, it.x0, bufs);
+          else
+            walk_staged<S, R, +1, true>(c, k, A, B, q, y0, y1, it.x0, bufs);
+        }
       } else {
         if (down)
           walk_direct<S, R, -1>(c, k, A, B, q, y0, y1);
