@@ -23,6 +23,7 @@ CASE_DEFAULTS = dict(
     Cp=1.0, Th=1.0, Tm=0.0, rho0=1.0,
     heater_center=0.5, heater_width=0.25,
     k0_g=NAN, k2_g=NAN, k0_f=NAN, k1_f=NAN,
+    solid_model=0, darcy_c=NAN, darcy_eps=NAN,
 )
 
 

@@ -26,6 +26,7 @@ W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 PARAM_DIMENSIONLESS = 0
 PARAM_LATTICE = 1
+SOLID_SCALE, SOLID_DARCY, SOLID_PBB = 0, 1, 2
 
 
 class Case(ctypes.Structure):
@@ -39,6 +40,7 @@ class Case(ctypes.Structure):
         ("heater_center", ctypes.c_double), ("heater_width", ctypes.c_double),
         ("k0_g", ctypes.c_double), ("k2_g", ctypes.c_double),
         ("k0_f", ctypes.c_double), ("k1_f", ctypes.c_double),
+        ("solid_model", ctypes.c_int), ("darcy_c", ctypes.c_double), ("darcy_eps", ctypes.c_double),
     ]
 
 
@@ -50,6 +52,7 @@ class Params(ctypes.Structure):
         ("k0_g", ctypes.c_double), ("k1_g", ctypes.c_double), ("k2_g", ctypes.c_double),
         ("k0_f", ctypes.c_double), ("k1_f", ctypes.c_double), ("k2_f", ctypes.c_double),
         ("heater_lo", ctypes.c_int), ("heater_hi", ctypes.c_int), ("n_heater", ctypes.c_int),
+        ("solid_model", ctypes.c_int), ("darcy_c", ctypes.c_double), ("darcy_eps", ctypes.c_double),
     ]
 
 
@@ -113,10 +116,11 @@ def _ptr(a):
 def make_case(nx, ny, *, periodic_x=False, periodic_y=False, param_mode=PARAM_DIMENSIONLESS,
               Ra=1e4, Pr=1.0, Ste=1.0, Ma=0.1, nu=0.0, alpha=0.0, gbeta=0.0, latent=0.0,
               Cp=1.0, Th=1.0, Tm=0.0, rho0=1.0, heater_center=0.5, heater_width=0.25,
-              k0_g=math.nan, k2_g=math.nan, k0_f=math.nan, k1_f=math.nan):
+              k0_g=math.nan, k2_g=math.nan, k0_f=math.nan, k1_f=math.nan,
+              solid_model=SOLID_SCALE, darcy_c=math.nan, darcy_eps=math.nan):
     return Case(nx, ny, int(periodic_x), int(periodic_y), param_mode, Ra, Pr, Ste, Ma,
                 nu, alpha, gbeta, latent, Cp, Th, Tm, rho0, heater_center, heater_width,
-                k0_g, k2_g, k0_f, k1_f)
+                k0_g, k2_g, k0_f, k1_f, int(solid_model), darcy_c, darcy_eps)
 
 
 def case_from_dict(d):

@@ -113,6 +113,14 @@ int or_derive(const or_case *cs, or_params *p) {
     }
   }
   p->n_heater = p->heater_hi >= p->heater_lo ? p->heater_hi - p->heater_lo + 1 : 0;
+  /* Solid-phase treatment of the flow (reading; the paper names none). */
+  if (cs->solid_model < OR_SOLID_SCALE || cs->solid_model > OR_SOLID_PBB) return -1;
+  p->solid_model = cs->solid_model;
+  p->darcy_c = isnan(cs->darcy_c) ? 1e3 : cs->darcy_c;
+  p->darcy_eps = isnan(cs->darcy_eps) ? 1e-3 : cs->darcy_eps;
+  if (!(p->darcy_c >= 0.0) || !isfinite(p->darcy_c) || !(p->darcy_eps > 0.0) ||
+      !isfinite(p->darcy_eps))
+    return -1;
   return 0;
 }
 
@@ -194,9 +202,20 @@ void or_collide_cell(const or_params *p, const double f[OR_Q], const double g[OR
   /* (b) temperature and liquid fraction */
   double T, fl;
   or_enthalpy_map(H, p->Cp, p->Tm, p->latent, &T, &fl);
-  /* (c) flow moments, buoyancy, velocity.  Readings: Boussinesq force
-   * rho0*g*beta*(T - Tm) along +y; the solid is immobilised by scaling the
-   * fluid velocity with the liquid fraction. */
+  /* (c) flow moments, buoyancy, velocity.  Reading: Boussinesq force
+   * rho0*g*beta*(T - Tm) along +y.  The solid is held still by one of three
+   * readings (or_case.solid_model):
+   *   SCALE: u = fl (j + F/2)/rho0, the fluid velocity scaled by the liquid
+   *          fraction;
+   *   DARCY: an enthalpy-porosity drag F_d = -A rho0 u with the Carman-Kozeny
+   *          factor A = C (1-fl)^2/(fl^3+eps), taken at the half step like
+   *          the body force, rho0 u = j + (F + F_d)/2, so
+   *          u = (j + F/2)/(rho0 (1 + A/2)); the collision is forced by
+   *          F + F_d;
+   *   PBB:   u = (j + F/2)/rho0 as for a free fluid; after the collision the
+   *          flow populations are partly bounced back, f_i <- (1 - ns) f_i* +
+   *          ns f_opp(i) with the pre-collision f and solid fraction
+   *          ns = 1 - fl. */
   double rho = 0.0, jx = 0.0, jy = 0.0;
   for (int i = 0; i < OR_Q; ++i) {
     rho += f[i];
@@ -205,8 +224,21 @@ void or_collide_cell(const or_params *p, const double f[OR_Q], const double g[OR
   }
   double Fx = 0.0;
   double Fy = p->rho0 * p->gbeta * (T - p->Tm);
-  double ux = fl * (jx + 0.5 * Fx) / p->rho0;
-  double uy = fl * (jy + 0.5 * Fy) / p->rho0;
+  double ux, uy, ns = 0.0;
+  if (p->solid_model == OR_SOLID_DARCY) {
+    double A = p->darcy_c * (1.0 - fl) * (1.0 - fl) / (fl * fl * fl + p->darcy_eps);
+    ux = (jx + 0.5 * Fx) / (p->rho0 * (1.0 + 0.5 * A));
+    uy = (jy + 0.5 * Fy) / (p->rho0 * (1.0 + 0.5 * A));
+    Fx -= A * p->rho0 * ux;
+    Fy -= A * p->rho0 * uy;
+  } else if (p->solid_model == OR_SOLID_PBB) {
+    ux = (jx + 0.5 * Fx) / p->rho0;
+    uy = (jy + 0.5 * Fy) / p->rho0;
+    ns = 1.0 - fl;
+  } else {
+    ux = fl * (jx + 0.5 * Fx) / p->rho0;
+    uy = fl * (jy + 0.5 * Fy) / p->rho0;
+  }
   /* (d) flow collision: Eq. (2) with (k0_f, k1_f, k2_f) plus a forcing term
    * projected on the first and second Hermite moments (reading). */
   double feq[OR_Q], force[OR_Q];
@@ -218,6 +250,8 @@ void or_collide_cell(const or_params *p, const double f[OR_Q], const double g[OR
                        (1.0 - 0.5 * p->k2_f) * qcontract(i, sxx, sxy, syy) / (2.0 * CS2 * CS2));
   }
   btrirt_update(f, feq, p->k0_f, p->k1_f, p->k2_f, force, fout);
+  if (p->solid_model == OR_SOLID_PBB)
+    for (int i = 0; i < OR_Q; ++i) fout[i] = (1.0 - ns) * fout[i] + ns * f[OPP[i]];
   /* (e) enthalpy collision: Eq. (2) with g_eq of Eq. (3). */
   double geq[OR_Q];
   or_geq(H, T, ux, uy, p->Cp, geq);

@@ -38,6 +38,14 @@ extern "C" {
 /* How the physical parameters are given. */
 enum { OR_PARAM_DIMENSIONLESS = 0, OR_PARAM_LATTICE = 1 };
 
+/* How the flow is held still in solid and mushy cells (the paper does not
+ * say; readings, see or_collide_cell):
+ *   OR_SOLID_SCALE: fluid velocity scaled by the liquid fraction;
+ *   OR_SOLID_DARCY: enthalpy-porosity drag -A rho0 u, A = C (1-fl)^2/(fl^3+eps);
+ *   OR_SOLID_PBB:   partial bounce-back of the flow populations with solid
+ *                   fraction 1 - fl. */
+enum { OR_SOLID_SCALE = 0, OR_SOLID_DARCY = 1, OR_SOLID_PBB = 2 };
+
 /* Problem statement.  Any relaxation rate left as NaN takes its default. */
 typedef struct {
   int nx, ny;               /* cells along x (horizontal) and y (vertical, y=0 heated bottom) */
@@ -49,6 +57,8 @@ typedef struct {
   double heater_center, heater_width; /* strip centre C and width D, fractions of nx */
   double k0_g, k2_g;        /* enthalpy rates; k1_g always follows Eq. (4) */
   double k0_f, k1_f;        /* flow rates; k2_f always follows the viscosity */
+  int solid_model;          /* OR_SOLID_* */
+  double darcy_c, darcy_eps; /* OR_SOLID_DARCY constants; NaN -> 1e3 and 1e-3 */
 } or_case;
 
 /* Lattice parameters derived from an or_case. */
@@ -58,6 +68,8 @@ typedef struct {
   double k0_g, k1_g, k2_g, k0_f, k1_f, k2_f;
   int heater_lo, heater_hi; /* heater cells x in [heater_lo, heater_hi] on row y=0; none if lo>hi */
   int n_heater;
+  int solid_model;
+  double darcy_c, darcy_eps;
 } or_params;
 
 typedef struct {

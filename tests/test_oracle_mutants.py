@@ -10,6 +10,7 @@ import pytest
 import oracle
 from oracle import build as obuild
 from tests import test_oracle_pins as pins
+from tests import test_oracle_solid as solid
 
 # (name, text in btrirt_oracle.c, replacement)
 MUTANTS = [
@@ -28,7 +29,7 @@ MUTANTS = [
     ("Eq. (5) default replaced by k2 = 1",
      "p->k2_g = isnan(cs->k2_g) ? 2.0 - p->k1_g : cs->k2_g;", "p->k2_g = isnan(cs->k2_g) ? 1.0 : cs->k2_g;"),
     ("full force in the velocity",
-     "double uy = fl * (jy + 0.5 * Fy) / p->rho0;", "double uy = fl * (jy + Fy) / p->rho0;"),
+     "uy = fl * (jy + 0.5 * Fy) / p->rho0;", "uy = fl * (jy + Fy) / p->rho0;"),
     ("transposed second moment",
      "m2xy += CX[j] * CY[j] * neq[j];", "m2xy += CX[j] * CX[j] * neq[j];"),
     ("heater strip one cell short",
@@ -48,6 +49,14 @@ MUTANTS = [
      "double Fy = p->rho0 * p->gbeta * (T - p->Tm);", "double Fy = p->rho0 * p->gbeta * (T - p->Th);"),
     ("k0 term missing",
      "out[i] = p[i] - k0 * neq[i] - (k1 - k0)", "out[i] = p[i] - 0.0 * neq[i] - (k1 - k0)"),
+    ("Darcy drag taken explicitly, not at the half step",
+     "uy = (jy + 0.5 * Fy) / (p->rho0 * (1.0 + 0.5 * A));", "uy = (jy + 0.5 * Fy) / p->rho0;"),
+    ("Carman-Kozeny factor without the square",
+     "p->darcy_c * (1.0 - fl) * (1.0 - fl)", "p->darcy_c * (1.0 - fl)"),
+    ("partial bounce-back with the liquid fraction as solid fraction",
+     "ns = 1.0 - fl;", "ns = fl;"),
+    ("partial bounce-back of the post-collision populations",
+     "ns * f[OPP[i]]", "ns * fout[OPP[i]]"),
 ]
 
 PIN_CHECKS = [
@@ -67,6 +76,9 @@ PIN_CHECKS = [
     pins.test_gaussian_variance_grows_at_twice_alpha_1d,
     pins.test_walled_cavity_budget_closes,
     pins.test_centred_heater_is_mirror_symmetric,
+    lambda: solid.test_darcy_velocity_is_the_mean_momentum_and_momentum_gains_the_total_force(0),
+    lambda: solid.test_partial_bounce_back_mixes_free_fluid_and_full_bounce_back(0),
+    lambda: solid.test_liquid_cell_is_a_free_fluid_under_every_reading(oracle.SOLID_DARCY),
 ]
 
 
