@@ -68,6 +68,21 @@ enum {
 typedef struct lbm_ctx lbm_ctx;
 
 /*
+ * How the solid and mushy cells hold the flow still.  The paper does not say;
+ * three readings are offered:
+ *   LBM_SOLID_SCALE  fluid velocity u = fl (j + F/2)/rho0, scaled by the
+ *                    liquid fraction (default);
+ *   LBM_SOLID_DARCY  enthalpy-porosity drag -A rho0 u with the Carman-Kozeny
+ *                    factor A = C (1 - fl)^2 / (fl^3 + eps), taken at the half
+ *                    step with the buoyancy: u = (j + F/2) / (rho0 (1 + A/2)),
+ *                    and the collision forced by buoyancy plus drag;
+ *   LBM_SOLID_PBB    partial bounce-back: u = (j + F/2)/rho0 as for a free
+ *                    fluid, then f_i <- (1 - ns) f_i* + ns f_opp(i) with the
+ *                    pre-collision populations and solid fraction ns = 1 - fl.
+ */
+enum { LBM_SOLID_SCALE = 0, LBM_SOLID_DARCY = 1, LBM_SOLID_PBB = 2 };
+
+/*
  * Problem statement of one cavity (Sec. 3.2).  Physical inputs come either
  * as dimensionless groups (param_mode = LBM_PARAM_DIMENSIONLESS: Ra, Pr, Ste
  * and the lattice Mach number Ma of the free-fall velocity, with the cavity
@@ -88,6 +103,9 @@ typedef struct {
   double heater_center, heater_width; /* strip centre C and width D as fractions of nx */
   double k0_g, k2_g, k0_f, k1_f;
   double T0, gauss_amp, gauss_sigma; /* LBM_INIT_LIQUID_T0 / LBM_INIT_GAUSSIAN */
+  int32_t solid_model;      /* LBM_SOLID_*: how the solid holds the flow still */
+  int32_t reserved;         /* 0 */
+  double darcy_c, darcy_eps; /* LBM_SOLID_DARCY constants C and eps; NaN -> 1e3 and 1e-3 */
 } lbm_case;
 
 /* Lattice parameters derived from a case (Eqs. (4)-(5) and the flow closure). */
@@ -96,6 +114,7 @@ typedef struct {
   double k0_g, k1_g, k2_g, k0_f, k1_f, k2_f;
   int32_t heater_lo, heater_hi, n_heater; /* heated cells x in [lo, hi] of row y = 0 */
   int32_t pitch;                          /* device row pitch in cells */
+  double darcy_c, darcy_eps;              /* drag constants in use (LBM_SOLID_DARCY) */
 } lbm_lattice;
 
 /* Per-cavity diagnostics of the current state, computed in FP64 with

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 LBM_FP64, LBM_FP32_SHIFTED = 0, 1
 LBM_PATTERN_AA, LBM_PATTERN_AB = 0, 1
+LBM_SOLID_SCALE, LBM_SOLID_DARCY, LBM_SOLID_PBB = 0, 1, 2
 LBM_PARAM_DIMENSIONLESS, LBM_PARAM_LATTICE = 0, 1
 LBM_INIT_SOLID_AT_TM, LBM_INIT_LIQUID_T0, LBM_INIT_GAUSSIAN = 0, 1, 2
 LBM_FIELD_T, LBM_FIELD_FL, LBM_FIELD_H, LBM_FIELD_UX, LBM_FIELD_UY, LBM_FIELD_RHO = 1, 2, 4, 8, 16, 32
@@ -56,6 +57,8 @@ class lbm_case(ctypes.Structure):
         ("heater_center", ctypes.c_double), ("heater_width", ctypes.c_double),
         ("k0_g", ctypes.c_double), ("k2_g", ctypes.c_double), ("k0_f", ctypes.c_double), ("k1_f", ctypes.c_double),
         ("T0", ctypes.c_double), ("gauss_amp", ctypes.c_double), ("gauss_sigma", ctypes.c_double),
+        ("solid_model", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("darcy_c", ctypes.c_double), ("darcy_eps", ctypes.c_double),
     ]
 
 
@@ -66,6 +69,7 @@ class lbm_lattice(ctypes.Structure):
         ("k0_f", ctypes.c_double), ("k1_f", ctypes.c_double), ("k2_f", ctypes.c_double),
         ("heater_lo", ctypes.c_int32), ("heater_hi", ctypes.c_int32), ("n_heater", ctypes.c_int32),
         ("pitch", ctypes.c_int32),
+        ("darcy_c", ctypes.c_double), ("darcy_eps", ctypes.c_double),
     ]
 
 
@@ -89,6 +93,7 @@ _CASE_DEFAULTS = dict(
     Cp=1.0, Th=1.0, Tm=0.0, rho0=1.0, heater_center=0.5, heater_width=0.25,
     k0_g=math.nan, k2_g=math.nan, k0_f=math.nan, k1_f=math.nan,
     T0=0.0, gauss_amp=0.0, gauss_sigma=1.0,
+    solid_model=0, reserved=0, darcy_c=math.nan, darcy_eps=math.nan,
 )
 CASE_FIELDS = tuple(name for name, _ in lbm_case._fields_)
 

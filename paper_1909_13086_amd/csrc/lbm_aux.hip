@@ -114,8 +114,18 @@ __device__ __forceinline__ Macro macros(const CavDev &c, const double (&f)[kQ],
   m.T = c.Tm + th;
   m.fl = fl;
   m.H = dH + c.Cp * c.Tm;
-  m.ux = fl * jx * c.inv_rho0;
-  m.uy = fl * (jy + 0.5 * Fy) * c.inv_rho0;
+  // fluid velocity of the solid model: scaled by fl, held by the drag
+  // (u = (fl^3 + eps)/D (j + F/2)/rho0, D = fl^3 + eps + C (1 - fl)^2 / 2),
+  // or free (bounce-back model)
+  double s = fl;
+  if (c.solid_model == kSolidDarcy) {
+    const double fl3e = fl * fl * fl + c.darcy_eps;
+    s = fl3e / (fl3e + 0.5 * c.darcy_c * (1.0 - fl) * (1.0 - fl));
+  } else if (c.solid_model == kSolidPbb) {
+    s = 1.0;
+  }
+  m.ux = s * jx * c.inv_rho0;
+  m.uy = s * (jy + 0.5 * Fy) * c.inv_rho0;
   m.rho = c.rho0 + drho;
   return m;
 }

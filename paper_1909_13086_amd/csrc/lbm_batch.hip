@@ -15,7 +15,7 @@ using namespace dev;
 // share that XCD's L2.  Cavity j advances in this launch only while
 // launch_index < active_steps(j); its storage parity is its chunk-start
 // parity flipped by the launch index.
-template <typename S, typename R>
+template <typename S, typename R, int MODEL>
 __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ cavs,
                                                     const BatchTile *__restrict__ tiles,
                                                     const int32_t *__restrict__ hdr,
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ c
     if (x >= c.nx) continue;
     for (int r = threadIdx.y; r < tile_rows; r += blockDim.y) {
       const int y = tile.y0 + r;
-      if (y < c.ny) update_cell<S, R>(c, k, mode, x, y);
+      if (y < c.ny) update_cell<S, R, MODEL>(c, k, mode, x, y);
     }
   }
 }
@@ -46,16 +46,21 @@ __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ c
 }  // namespace
 
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
-                             const int32_t *hdr_dev, int tile_cap, int precision, int tile_bx,
-                             int tile_rows, int launch_index, int grid, hipStream_t s) {
+                             const int32_t *hdr_dev, int tile_cap, int precision, int model,
+                             int tile_bx, int tile_rows, int launch_index, int grid,
+                             hipStream_t s) {
   const int by = 256 / tile_bx;
   const dim3 block(tile_bx, by < 1 ? 1 : by);
-  if (precision == 0)
-    hipLaunchKernelGGL((k_step_batch<double, double>), dim3(grid), block, 0, s, cavs_dev,
-                       tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
-  else
-    hipLaunchKernelGGL((k_step_batch<float, float>), dim3(grid), block, 0, s, cavs_dev,
-                       tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+  with_model(model, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    if (precision == 0)
+      hipLaunchKernelGGL((k_step_batch<double, double, M>), dim3(grid), block, 0, s, cavs_dev,
+                         tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+    else
+      hipLaunchKernelGGL((k_step_batch<float, float, M>), dim3(grid), block, 0, s, cavs_dev,
+                         tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+    return 0;
+  });
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace lbm {
 namespace dev {
@@ -61,6 +62,7 @@ struct Coef {
   R hk1f, hk2f;            // 1 - k1/2, 1 - k2/2 for the force terms
   R Cp, inv_Cp, L, inv_L, rho0, inv_rho0, gb, Tm;
   R c2[3];                 // 2 w_i Cp (Th - Tm) for w = 4/9 (unused), 1/9, 1/36
+  R darcy_c, darcy_eps;    // drag constants of the Darcy solid model
 
   __device__ explicit Coef(const CavDev &c) {
     k0g = R(c.k0g);
@@ -84,6 +86,8 @@ struct Coef {
     c2[0] = R(2.0 * wgt(0) * c.Cp * c.dT);
     c2[1] = R(2.0 * wgt(1) * c.Cp * c.dT);
     c2[2] = R(2.0 * wgt(5) * c.Cp * c.dT);
+    darcy_c = R(c.darcy_c);
+    darcy_eps = R(c.darcy_eps);
   }
   __device__ R anti(int i) const { return i == 0 ? c2[0] : (i <= 4 ? c2[1] : c2[2]); }
 };
@@ -118,6 +122,17 @@ __device__ __forceinline__ void relax_pair(R &pp, R &pm, R omk0, R k0, R E, R O,
   pm = omk0 * pm + (even - odd);
 }
 
+// The same followed by partial bounce-back with solid fraction ns: each
+// member mixes its post-collision value with its partner's pre-collision one.
+template <typename R>
+__device__ __forceinline__ void relax_pair_pbb(R &pp, R &pm, R omk0, R k0, R E, R O, R t1, R t2,
+                                               R ns) {
+  const R pp0 = pp, pm0 = pm;
+  relax_pair<R>(pp, pm, omk0, k0, E, O, t1, t2);
+  pp = (R(1) - ns) * pp + ns * pm0;
+  pm = (R(1) - ns) * pm + ns * pp0;
+}
+
 // The four pairs of D2Q9 directions, "+" member first: (1, 3) along x,
 // (2, 4) along y, (5, 7) along (1, 1), (6, 8) along (-1, 1).  For each pair,
 // c.u, c.a1 and Q:a2 of the "+" member.
@@ -145,8 +160,9 @@ __device__ constexpr int pair_plus(int p) { return p == 0 ? 1 : (p == 1 ? 2 : (p
 __device__ constexpr int pair_minus(int p) { return p == 0 ? 3 : (p == 1 ? 4 : (p == 2 ? 7 : 8)); }
 __device__ constexpr double pair_w(int p) { return p < 2 ? 1.0 / 9.0 : 1.0 / 36.0; }
 
-// One B-TriRT collision of a cell, shifted populations in place.
-template <typename R>
+// One B-TriRT collision of a cell, shifted populations in place.  MODEL is
+// the solid-phase treatment of the flow (kSolid*), fixed at compile time.
+template <typename R, int MODEL>
 __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]) {
   constexpr R third = R(1.0 / 3.0);
   constexpr R w0 = R(4.0 / 9.0);
@@ -159,9 +175,28 @@ __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]
   const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const R Fy = k.gb * th;
-  const R ux = fl * jx * k.inv_rho0;
-  const R uy = fl * (jy + R(0.5) * Fy) * k.inv_rho0;
+  const R Fb = k.gb * th;  // buoyancy, along +y
+  R ux, uy, Fx = R(0), Fy = Fb;
+  if constexpr (MODEL == kSolidDarcy) {
+    // rho0 u = j + (Fb - A rho0 u)/2, A = C (1 - fl)^2 / (fl^3 + eps): with
+    // D = fl^3 + eps + C (1 - fl)^2 / 2, u = (fl^3 + eps)/D (j + Fb/2)/rho0
+    // and the drag -A rho0 u = -C (1 - fl)^2 / D (j + Fb/2)
+    const R ml = R(1) - fl;
+    const R fl3e = fl * fl * fl + k.darcy_eps;
+    const R cm = k.darcy_c * ml * ml;
+    const R rD = R(1) / (fl3e + R(0.5) * cm);
+    const R qy = jy + R(0.5) * Fb;
+    const R s = fl3e * rD * k.inv_rho0;
+    ux = s * jx;
+    uy = s * qy;
+    Fx = -(cm * rD) * jx;
+    Fy = Fb - (cm * rD) * qy;
+  } else {
+    // velocity scaled by the liquid fraction, or free (bounce-back model)
+    const R s = MODEL == kSolidPbb ? R(1) : fl;
+    ux = s * jx * k.inv_rho0;
+    uy = s * (jy + R(0.5) * Fb) * k.inv_rho0;
+  }
   // (d) flow collision with the Hermite-projected force
   {
     const R d = (f[5] + f[6]) + (f[7] + f[8]);
@@ -173,25 +208,38 @@ __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]
     const R m2xx = pxx - (r3 + k.rho0 * ux * ux);
     const R m2yy = pyy - (r3 + k.rho0 * uy * uy);
     const R m2xy = pxy - k.rho0 * ux * uy;
-    const R a1x = k.dk1f * m1x;
+    // the force has an x part only under the drag
+    constexpr bool fx = MODEL == kSolidDarcy;
+    const R a1x = fx ? k.dk1f * m1x - k.hk1f * Fx : k.dk1f * m1x;
     const R a1y = k.dk1f * m1y - k.hk1f * Fy;
-    const R a2xx = k.dk2f * m2xx;
-    const R a2xy = k.dk2f * m2xy - k.hk2f * (ux * Fy);
+    const R a2xx = fx ? k.dk2f * m2xx - k.hk2f * (R(2) * ux * Fx) : k.dk2f * m2xx;
+    const R a2xy = k.dk2f * m2xy - k.hk2f * (fx ? ux * Fy + uy * Fx : ux * Fy);
     const R a2yy = k.dk2f * m2yy - k.hk2f * (R(2) * uy * Fy);
     const R uu15 = R(1.5) * (ux * ux + uy * uy);
-    {
-      const R feq0 = w0 * (drho - k.rho0 * uu15);
-      const R qa0 = -(a2xx + a2yy) * third;
-      f[0] = k.omk0f * f[0] + (k.k0f * feq0 - R(4.5) * w0 * qa0);
-    }
+    const R feq0 = w0 * (drho - k.rho0 * uu15);
+    const R qa0 = -(a2xx + a2yy) * third;
     const PairTerms<R> t(ux, uy, a1x, a1y, a2xx, a2xy, a2yy);
+    if constexpr (MODEL == kSolidPbb) {
+      const R ns = R(1) - fl;
+      f[0] = (R(1) - ns) * (k.omk0f * f[0] + (k.k0f * feq0 - R(4.5) * w0 * qa0)) + ns * f[0];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const R w = R(pair_w(p));
-      const R E = w * (drho + k.rho0 * (R(4.5) * t.cu[p] * t.cu[p] - uu15));
-      const R O = R(3) * w * k.rho0 * t.cu[p];
-      relax_pair<R>(f[pair_plus(p)], f[pair_minus(p)], k.omk0f, k.k0f, E, O, R(3) * w * t.c1[p],
-                    R(4.5) * w * t.qa[p]);
+      for (int p = 0; p < 4; ++p) {
+        const R w = R(pair_w(p));
+        const R E = w * (drho + k.rho0 * (R(4.5) * t.cu[p] * t.cu[p] - uu15));
+        const R O = R(3) * w * k.rho0 * t.cu[p];
+        relax_pair_pbb<R>(f[pair_plus(p)], f[pair_minus(p)], k.omk0f, k.k0f, E, O,
+                          R(3) * w * t.c1[p], R(4.5) * w * t.qa[p], ns);
+      }
+    } else {
+      f[0] = k.omk0f * f[0] + (k.k0f * feq0 - R(4.5) * w0 * qa0);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const R w = R(pair_w(p));
+        const R E = w * (drho + k.rho0 * (R(4.5) * t.cu[p] * t.cu[p] - uu15));
+        const R O = R(3) * w * k.rho0 * t.cu[p];
+        relax_pair<R>(f[pair_plus(p)], f[pair_minus(p)], k.omk0f, k.k0f, E, O, R(3) * w * t.c1[p],
+                      R(4.5) * w * t.qa[p]);
+      }
     }
   }
   // (e) enthalpy collision with the equilibrium of Eq. (3)
@@ -366,7 +414,7 @@ __device__ __forceinline__ void add_strip_flux(const CavDev &c, const Coef<R> &k
 
 // One lattice update of cell (x, y) for the given storage mode.
 //   mode 0: A-A even, mode 1: A-A odd, mode 2: two lattices (src -> dst)
-template <typename S, typename R, bool NT = false>
+template <typename S, typename R, int MODEL, bool NT = false>
 __device__ __forceinline__ void update_cell(const CavDev &c, const Coef<R> &k, int mode, int x,
                                             int y) {
   const int64_t idx = cell_base(c, x, y);
@@ -374,21 +422,31 @@ __device__ __forceinline__ void update_cell(const CavDev &c, const Coef<R> &k, i
   if (mode == 0) {
     S *P = static_cast<S *>(c.pop[0]);
     load_natural<S, R, NT>(P, c.plane, idx, f, g);
-    collide<R>(k, f, g);
+    collide<R, MODEL>(k, f, g);
     store_swapped<S, R, NT>(P, c.plane, idx, f, g);
   } else if (mode == 1) {
     S *P = static_cast<S *>(c.pop[0]);
     load_gather<S, R, NT>(c, k, P, x, y, idx, f, g);
-    collide<R>(k, f, g);
+    collide<R, MODEL>(k, f, g);
     store_scatter<S, R, NT>(c, k, P, x, y, idx, f, g);
   } else {
     const S *A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
     S *B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
     load_natural<S, R, NT>(A, c.plane, idx, f, g);
-    collide<R>(k, f, g);
+    collide<R, MODEL>(k, f, g);
     store_scatter<S, R, NT>(c, k, B, x, y, idx, f, g);
   }
   if (!c.periodic_y && heated(c, x, y)) add_strip_flux<R>(c, k, x, g);
+}
+
+// Calls fn(std::integral_constant<int, MODEL>) for the cavity's solid model.
+template <typename Fn>
+__host__ __device__ inline auto with_model(int model, Fn &&fn) {
+  switch (model) {
+    case kSolidDarcy: return fn(std::integral_constant<int, kSolidDarcy>{});
+    case kSolidPbb: return fn(std::integral_constant<int, kSolidPbb>{});
+    default: return fn(std::integral_constant<int, kSolidScale>{});
+  }
 }
 
 __device__ __forceinline__ int storage_mode(const CavDev &c) {

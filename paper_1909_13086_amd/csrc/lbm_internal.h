@@ -13,6 +13,8 @@ constexpr int kQ = 9;
 constexpr int kPlanes = 2 * kQ;  // f_0..f_8 then g_0..g_8
 constexpr int kWave = 64;
 constexpr int kXcds = 8;
+// How the solid holds the flow still (values of LBM_SOLID_* in lbm.h).
+constexpr int kSolidScale = 0, kSolidDarcy = 1, kSolidPbb = 2;
 
 // Everything a kernel needs to advance or inspect one cavity.  Built on the
 // host from a validated case; passed by value (single cavity) or read from a
@@ -24,7 +26,7 @@ struct CavDev {
   int32_t parity;      // in-place pattern: 0 natural, 1 swapped; AB: index of current lattice
   int32_t pattern;     // 0 in place (A-A), 1 two lattices
   int32_t active_steps; // batched launch: launches of the current chunk that advance it
-  int32_t pad_;
+  int32_t solid_model;  // LBM_SOLID_*
   int64_t plane;       // elements between consecutive population planes of a cell
   // relaxation rates of Eq. (2)
   double k0g, k1g, k2g, k0f, k1f, k2f;
@@ -33,6 +35,7 @@ struct CavDev {
   double dT;           // Th - Tm
   double Tm;
   double alpha;
+  double darcy_c, darcy_eps;  // LBM_SOLID_DARCY: A = C (1 - fl)^2 / (fl^3 + eps)
   void *pop[2];        // population planes (pop[1] only for two lattices)
   double *cumq;        // per-column strip enthalpy summed over steps, nx doubles
 };
@@ -88,15 +91,17 @@ hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hip
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
 // entries (the kernel ignores a header that points outside them).
+// model: the solid model shared by every cavity of the tile list (kSolid*).
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
-                             const int32_t *hdr_dev, int tile_cap, int precision, int tile_bx,
-                             int tile_rows, int launch_index, int grid, hipStream_t s);
+                             const int32_t *hdr_dev, int tile_cap, int precision, int model,
+                             int tile_bx, int tile_rows, int launch_index, int grid,
+                             hipStream_t s);
 // Batched two-step launch over wavefront items {cavity, strip origin x0,
 // segment origin y0, segment index} of two-lattice cavities: launch j
 // advances cavity c by two steps while 2 j + 2 <= active_steps(c), by one
 // step when 2 j + 1 == active_steps(c), else leaves it.
 hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
-                              const int32_t *hdr_dev, int item_cap, int precision,
+                              const int32_t *hdr_dev, int item_cap, int precision, int model,
                               const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s);
 // Workgroups of a batched two-step launch that fill the device once.
 int step2_batch_grid(int num_cus);

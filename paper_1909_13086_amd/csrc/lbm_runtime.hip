@@ -54,6 +54,10 @@ bool rate_ok(double k) { return std::isfinite(k) && k > 0.0 && k < 2.0; }
 // the free-fall velocity sqrt(g beta dT ny) equals Ma*cs, Ste = Cp dT / L.
 // Eq. (4): 1/k1 = alpha/cs^2 + 1/2; Eq. (5): k2 = 2 - k1 unless given.  The
 // flow's stress moment carries the viscosity the same way.
+static_assert(lbm::kSolidScale == LBM_SOLID_SCALE && lbm::kSolidDarcy == LBM_SOLID_DARCY &&
+                  lbm::kSolidPbb == LBM_SOLID_PBB,
+              "solid model codes");
+
 int derive(const lbm_case *cs, lbm_lattice *out, std::string &why) {
   std::memset(out, 0, sizeof(*out));
   if (!cs) { why = "case is NULL"; return LBM_EINVAL; }
@@ -130,6 +134,15 @@ int derive(const lbm_case *cs, lbm_lattice *out, std::string &why) {
     }
   }
   out->n_heater = out->heater_hi >= out->heater_lo ? out->heater_hi - out->heater_lo + 1 : 0;
+  if (cs->solid_model < LBM_SOLID_SCALE || cs->solid_model > LBM_SOLID_PBB) {
+    why = "unknown solid model"; return LBM_EINVAL;
+  }
+  out->darcy_c = std::isnan(cs->darcy_c) ? 1e3 : cs->darcy_c;
+  out->darcy_eps = std::isnan(cs->darcy_eps) ? 1e-3 : cs->darcy_eps;
+  if (!(out->darcy_c >= 0.0) || !std::isfinite(out->darcy_c) || !(out->darcy_eps > 0.0) ||
+      !std::isfinite(out->darcy_eps)) {
+    why = "Darcy constant must be >= 0 and eps > 0"; return LBM_EINVAL;
+  }
   if (cs->init == LBM_INIT_LIQUID_T0 && !std::isfinite(cs->T0)) {
     why = "T0 must be finite"; return LBM_EINVAL;
   }
@@ -196,9 +209,9 @@ struct Batch {
   BatchTile *tiles_host = nullptr;
   int32_t *hdr_host = nullptr;
   std::vector<int> members;       // slot ids in cavity-array order
-  std::vector<int> group_precs;   // per group: bit 2 p + kind set when it holds such launches
-                                  // (kind 0: one step per launch over tiles, kind 1: two-step
-                                  // launches over strip segments)
+  std::vector<int> group_precs;   // per group: bit launch_bit(p, kind, model) set when it holds
+                                  // such launches (kind 0: one step per launch over tiles,
+                                  // kind 1: two-step launches over strip segments)
   bool dirty = true;
   hipGraphExec_t graph = nullptr; // valid while the device buffers and the group shape stay
   int graph_chunk = 0;
@@ -280,6 +293,9 @@ CavDev make_dev(const lbm_case *cs, const lbm_lattice &lat, const Layout &lay, v
   d.parity = 0;
   d.pattern = cs->pattern;
   d.active_steps = 0;
+  d.solid_model = cs->solid_model;
+  d.darcy_c = lat.darcy_c;
+  d.darcy_eps = lat.darcy_eps;
   d.plane = lbm::kWave;  // blocked layout: planes of a 64-cell chunk are 64 elements apart
   d.k0g = lat.k0_g;
   d.k1g = lat.k1_g;
@@ -469,8 +485,13 @@ constexpr int kBatchTileX = 64;
 constexpr int kBatchTileRows = 16;
 constexpr int kStrip2Cols = lbm::kWave - 2;  // owned columns of a two-step wavefront
 
-// Header slot of (cache group, precision, kind) in the batch header array.
-int hdr_index(int g, int prec, int kind) { return ((g * 2 + prec) * 2 + kind) * 2; }
+// Launches of a cache group come per precision, kind (one-step tiles or
+// two-step segments) and solid model; each has a {first, count} header.
+constexpr int kLaunchKinds = 2 * 2 * 3;
+int launch_bit(int prec, int kind, int model) { return (prec * 2 + kind) * 3 + model; }
+int hdr_index(int g, int prec, int kind, int model) {
+  return (g * kLaunchKinds + launch_bit(prec, kind, model)) * 2;
+}
 
 void free_batch(lbm_ctx *c) {
   Batch &b = c->batch;
@@ -525,13 +546,13 @@ int rebuild_batch(lbm_ctx *c) {
   };
   size_t ntiles = 0;
   for (int id : b.members) ntiles += items_of(c->slots[id]);
-  const size_t nhdr = (size_t)std::max(ngroups, 1) * 8;
+  const size_t nhdr = (size_t)std::max(ngroups, 1) * kLaunchKinds * 2;
   HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
   if (ncav > b.cav_cap || ntiles > b.tile_cap || nhdr > b.hdr_cap) {
     free_batch(c);
     b.cav_cap = std::max<size_t>(ncav, c->slots.size());
     b.tile_cap = std::max<size_t>(ntiles * 2, 4096);
-    b.hdr_cap = std::max<size_t>(nhdr * 2, 8 * 64);
+    b.hdr_cap = std::max<size_t>(nhdr * 2, (size_t)kLaunchKinds * 2 * 64);
     HIP_TRY(hipMalloc(&b.cavs_dev, b.cav_cap * sizeof(CavDev)));
     HIP_TRY(hipMalloc(&b.tiles_dev, b.tile_cap * sizeof(BatchTile)));
     HIP_TRY(hipMalloc(&b.hdr_dev, b.hdr_cap * sizeof(int32_t)));
@@ -545,26 +566,29 @@ int rebuild_batch(lbm_ctx *c) {
   for (int g = 0; g < ngroups; ++g) {
     for (int prec = 0; prec < 2; ++prec) {
       for (int kind = 0; kind < 2; ++kind) {
-        const size_t first = t;
-        for (size_t j = 0; j < ncav; ++j) {
-          if (group_of[j] != g) continue;
-          const Slot &s = c->slots[b.members[j]];
-          if (s.cs.precision != prec || (int)fused(c, s) != kind) continue;
-          if (kind == 0) {
-            for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
-              for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
-                b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
-          } else {
-            const int seg = c->launch[prec].seg;
-            for (int y0 = 0, k = 0; y0 < s.cs.ny; y0 += seg, ++k)
-              for (int x0 = 0; x0 < s.cs.nx; x0 += kStrip2Cols)
-                b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, k};
+        for (int model = 0; model < 3; ++model) {
+          const size_t first = t;
+          for (size_t j = 0; j < ncav; ++j) {
+            if (group_of[j] != g) continue;
+            const Slot &s = c->slots[b.members[j]];
+            if (s.cs.precision != prec || (int)fused(c, s) != kind || s.cs.solid_model != model)
+              continue;
+            if (kind == 0) {
+              for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
+                for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
+                  b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
+            } else {
+              const int seg = c->launch[prec].seg;
+              for (int y0 = 0, k = 0; y0 < s.cs.ny; y0 += seg, ++k)
+                for (int x0 = 0; x0 < s.cs.nx; x0 += kStrip2Cols)
+                  b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, k};
+            }
           }
+          const int h = hdr_index(g, prec, kind, model);
+          b.hdr_host[h] = (int32_t)first;
+          b.hdr_host[h + 1] = (int32_t)(t - first);
+          if (t > first) b.group_precs[g] |= 1 << launch_bit(prec, kind, model);
         }
-        const int h = hdr_index(g, prec, kind);
-        b.hdr_host[h] = (int32_t)first;
-        b.hdr_host[h + 1] = (int32_t)(t - first);
-        if (t > first) b.group_precs[g] |= 1 << (prec * 2 + kind);
       }
     }
   }
@@ -572,7 +596,8 @@ int rebuild_batch(lbm_ctx *c) {
     HIP_TRY(hipMemcpyAsync(b.tiles_dev, b.tiles_host, t * sizeof(BatchTile),
                            hipMemcpyHostToDevice, c->stream));
   if (ngroups > 0)
-    HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host, (size_t)ngroups * 8 * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(b.hdr_dev, b.hdr_host,
+                           (size_t)ngroups * kLaunchKinds * 2 * sizeof(int32_t),
                            hipMemcpyHostToDevice, c->stream));
   b.dirty = false;
   return LBM_OK;
@@ -588,16 +613,20 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
   for (int g = 0; g < (int)b.group_precs.size() && err == hipSuccess; ++g) {
     for (int k = 0; k < chunk && err == hipSuccess; ++k)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-        if (b.group_precs[g] & (1 << (prec * 2)))
-          err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + hdr_index(g, prec, 0),
-                                       (int)b.tile_cap, prec, kBatchTileX, kBatchTileRows, k,
-                                       batch_grid(c), c->stream);
+        for (int model = 0; model < 3 && err == hipSuccess; ++model)
+          if (b.group_precs[g] & (1 << launch_bit(prec, 0, model)))
+            err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev,
+                                         b.hdr_dev + hdr_index(g, prec, 0, model), (int)b.tile_cap,
+                                         prec, model, kBatchTileX, kBatchTileRows, k,
+                                         batch_grid(c), c->stream);
     for (int j = 0; j < (chunk + 1) / 2 && err == hipSuccess; ++j)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-        if (b.group_precs[g] & (1 << (prec * 2 + 1)))
-          err = lbm::launch_step2_batch(b.cavs_dev, b.tiles_dev, b.hdr_dev + hdr_index(g, prec, 1),
-                                        (int)b.tile_cap, prec, c->launch[prec], j,
-                                        lbm::step2_batch_grid(c->num_cus), c->stream);
+        for (int model = 0; model < 3 && err == hipSuccess; ++model)
+          if (b.group_precs[g] & (1 << launch_bit(prec, 1, model)))
+            err = lbm::launch_step2_batch(b.cavs_dev, b.tiles_dev,
+                                          b.hdr_dev + hdr_index(g, prec, 1, model),
+                                          (int)b.tile_cap, prec, model, c->launch[prec], j,
+                                          lbm::step2_batch_grid(c->num_cus), c->stream);
   }
   return err;
 }

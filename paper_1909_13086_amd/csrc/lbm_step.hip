@@ -11,7 +11,7 @@ using namespace dev;
 // one column.  order bit 0: consecutive tiles go to one XCD (contiguous bands
 // per XCD share its L2 at tile edges); bit 1: walk the tiles backwards on odd
 // storage parity.
-template <typename S, typename R, int CPL, bool NT>
+template <typename S, typename R, int CPL, bool NT, int MODEL>
 __global__ __launch_bounds__(256) void k_step(CavDev c, int tiles_x, int order) {
   const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
   const int tx = b % tiles_x, ty = b / tiles_x;
@@ -23,11 +23,11 @@ __global__ __launch_bounds__(256) void k_step(CavDev c, int tiles_x, int order) 
 #pragma unroll
   for (int r = 0; r < CPL; ++r) {
     const int y = ybase + r * blockDim.y;
-    if (y < c.ny) update_cell<S, R, NT>(c, k, mode, x, y);
+    if (y < c.ny) update_cell<S, R, MODEL, NT>(c, k, mode, x, y);
   }
 }
 
-template <typename S, typename R, bool NT>
+template <typename S, typename R, bool NT, int MODEL>
 hipError_t dispatch_cpl(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int tiles_x = (c.nx + cfg.bx - 1) / cfg.bx;
   const int rows = cfg.by * cfg.cpl;
@@ -36,9 +36,9 @@ hipError_t dispatch_cpl(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const dim3 grid(tiles_x * tiles_y);
   const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0);
   switch (cfg.cpl) {
-    case 1: hipLaunchKernelGGL((k_step<S, R, 1, NT>), grid, block, 0, s, c, tiles_x, order); break;
-    case 2: hipLaunchKernelGGL((k_step<S, R, 2, NT>), grid, block, 0, s, c, tiles_x, order); break;
-    case 4: hipLaunchKernelGGL((k_step<S, R, 4, NT>), grid, block, 0, s, c, tiles_x, order); break;
+    case 1: hipLaunchKernelGGL((k_step<S, R, 1, NT, MODEL>), grid, block, 0, s, c, tiles_x, order); break;
+    case 2: hipLaunchKernelGGL((k_step<S, R, 2, NT, MODEL>), grid, block, 0, s, c, tiles_x, order); break;
+    case 4: hipLaunchKernelGGL((k_step<S, R, 4, NT, MODEL>), grid, block, 0, s, c, tiles_x, order); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -46,7 +46,10 @@ hipError_t dispatch_cpl(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 
 template <typename S, typename R>
 hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
-  return cfg.nt ? dispatch_cpl<S, R, true>(c, cfg, s) : dispatch_cpl<S, R, false>(c, cfg, s);
+  return with_model(c.solid_model, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    return cfg.nt ? dispatch_cpl<S, R, true, M>(c, cfg, s) : dispatch_cpl<S, R, false, M>(c, cfg, s);
+  });
 }
 
 }  // namespace

@@ -106,10 +106,10 @@ __device__ __forceinline__ Col make_col(const CavDev &c, int x, int lane, int y0
 
 // First step of a loaded row: collision, plus the strip flux of a heated
 // bottom cell's first step.
-template <typename R>
+template <typename R, int MODEL>
 __device__ __forceinline__ void first_collide(const CavDev &c, const Coef<R> &k, const Col &q, int r,
                                               R (&f)[kQ], R (&g)[kQ]) {
-  collide<R>(k, f, g);
+  collide<R, MODEL>(k, f, g);
   if (r == 0 && q.strip_flux) add_strip_flux<R>(c, k, q.x, g);
 }
 
@@ -123,7 +123,7 @@ __device__ __forceinline__ void zero_row(R (&f)[kQ], R (&g)[kQ]) {
 // applied (WALLS = false: the wavefront's cells and their neighbours are all
 // inside the cavity, no link crosses a wall), then collided (result in pf,
 // pg).
-template <typename R, int D, bool WALLS = true>
+template <typename R, int D, bool WALLS, int MODEL>
 __device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k, const Col &q, int y,
                                                const R (&cf)[kQ], const R (&cg)[kQ],
                                                const R (&nf)[kQ], const R (&ng)[kQ],
@@ -161,7 +161,7 @@ __device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k
     pf[i] = vf;
     pg[i] = vg;
   }
-  collide<R>(k, pf, pg);
+  collide<R, MODEL>(k, pf, pg);
 }
 
 // Post-collision populations of an interior cell pushed to its neighbours'
@@ -227,7 +227,7 @@ __device__ __forceinline__ void slide(R (&af)[3], R (&ag)[3], R (&cf)[kQ], R (&c
 // -1 downwards from y1-1), each row loaded from A when needed.  Adjacent
 // segments walking in opposite directions reach the two halo rows they share
 // at the same point of their walks, so the second reader finds them in L2.
-template <typename S, typename R, int D>
+template <typename S, typename R, int D, int MODEL>
 __device__ __forceinline__ void walk_direct(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
                                             S *__restrict__ B, const Col &q, int y0, int y1) {
   auto first_step = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
@@ -237,7 +237,7 @@ __device__ __forceinline__ void walk_direct(const CavDev &c, const Coef<R> &k, c
       return;
     }
     load_natural<S, R>(A, c.plane, cell_base(c, q.xw, row_wrap(c, r)), f, g);
-    first_collide<R>(c, k, q, r, f, g);
+    first_collide<R, MODEL>(c, k, q, r, f, g);
   };
   const int ys = D > 0 ? y0 : y1 - 1;
   const int ye = D > 0 ? y1 : y0 - 1;
@@ -250,7 +250,7 @@ __device__ __forceinline__ void walk_direct(const CavDev &c, const Coef<R> &k, c
   for (int y = ys; y != ye; y += D) {
     first_step(y + D, nf, ng);
     R pf[kQ], pg[kQ];
-    second_collide<R, D>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
+    second_collide<R, D, true, MODEL>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
     emit<S, R>(c, k, B, q, y, pf, pg);
     slide<D>(af, ag, cf, cg, nf, ng);
   }
@@ -352,7 +352,7 @@ __device__ __forceinline__ void read_row(const S *buf, int lane, R (&f)[kQ], R (
 // copy of row k + 1 is issued into the buffer that row k - 1 has left, before
 // row k is read and collided; it is waited for before the stores of that
 // iteration are issued, so the stores never delay a later wait.
-template <typename S, typename R, int D, bool WALLS>
+template <typename S, typename R, int D, bool WALLS, int MODEL>
 __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
                                             S *__restrict__ B, const Col &q, int y0, int y1, int x0,
                                             S *bufs) {
@@ -369,7 +369,7 @@ __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, c
       return;
     }
     read_row<S, R>(buf(b), lane, f, g);
-    first_collide<R>(c, k, q, r, f, g);
+    first_collide<R, MODEL>(c, k, q, r, f, g);
   };
 
   const int ys = D > 0 ? y0 : y1 - 1;
@@ -392,7 +392,7 @@ __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, c
     if (y + D != ye) issue(y + 2 * D, b ^ 1);
     first_step(y + D, b, nf, ng);
     R pf[kQ], pg[kQ];
-    second_collide<R, D, WALLS>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
+    second_collide<R, D, WALLS, MODEL>(c, k, q, y, cf, cg, nf, ng, af, ag, pf, pg);
     wait_vm();
     emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
     slide<D>(af, ag, cf, cg, nf, ng);
@@ -401,7 +401,7 @@ __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, c
 
 // order: bit 0 XCD bands, bit 1 tiles walked backwards on odd parity,
 // bit 2 odd segments walked downwards
-template <typename S, typename R, bool STAGED>
+template <typename S, typename R, bool STAGED, int MODEL>
 __global__ __launch_bounds__(STAGED ? kStagedWaves * kWave : kDirectWaves * kWave)
 __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
     CavDev c, int strips_x, int nseg, int seg_rows, int order) {
@@ -426,20 +426,20 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
     const bool inner = interior_segment(c, x0, y0, y1);
     if (down) {
       if (inner)
-        walk_staged<S, R, -1, false>(c, k, A, B, q, y0, y1, x0, bufs);
+        walk_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
       else
-        walk_staged<S, R, -1, true>(c, k, A, B, q, y0, y1, x0, bufs);
+        walk_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
     } else {
       if (inner)
-        walk_staged<S, R, +1, false>(c, k, A, B, q, y0, y1, x0, bufs);
+        walk_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
       else
-        walk_staged<S, R, +1, true>(c, k, A, B, q, y0, y1, x0, bufs);
+        walk_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
     }
   } else {
     if (down)
-      walk_direct<S, R, -1>(c, k, A, B, q, y0, y1);
+      walk_direct<S, R, -1, MODEL>(c, k, A, B, q, y0, y1);
     else
-      walk_direct<S, R, +1>(c, k, A, B, q, y0, y1);
+      walk_direct<S, R, +1, MODEL>(c, k, A, B, q, y0, y1);
   }
 }
 
@@ -452,8 +452,11 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int per_block = STAGED ? kStagedWaves : kDirectWaves;
   const dim3 grid((waves + per_block - 1) / per_block);
   const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
-  hipLaunchKernelGGL((k_step2<S, R, STAGED>), grid, dim3(per_block * kWave), 0, s, c, strips_x, nseg,
-                     cfg.seg, order);
+  with_model(c.solid_model, [&](auto m) {
+    hipLaunchKernelGGL((k_step2<S, R, STAGED, decltype(m)::value>), grid, dim3(per_block * kWave), 0,
+                       s, c, strips_x, nseg, cfg.seg, order);
+    return 0;
+  });
   return hipGetLastError();
 }
 
@@ -463,7 +466,7 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 // device array, so a captured launch stays valid when cavities join or
 // leave.  The storage parity in launch j is the chunk-start parity flipped j
 // times: every earlier launch of the chunk advanced the cavity.
-template <typename S, typename R, bool STAGED>
+template <typename S, typename R, bool STAGED, int MODEL>
 __global__ __launch_bounds__(STAGED ? kStagedWaves * kWave : kDirectWaves * kWave)
 __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restrict__ cavs,
                                                            const BatchTile *__restrict__ items,
@@ -499,40 +502,44 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restr
         const bool inner = interior_segment(c, it.x0, y0, y1);
         if (down) {
           if (inner)
-            walk_staged<S, R, -1, false>(c, k, A, B, q, y0, y1, it.x0, bufs);
+            walk_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, it.x0, bufs);
           else
-            walk_staged<S, R, -1, true>(c, k, A, B, q, y0, y1, it.x0, bufs);
+            walk_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, it.x0, bufs);
         } else {
           if (inner)
-            walk_staged<S, R, +1, false>(c, k, A, B, q, y0, y1, it.x0, bufs);
+            walk_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, it.x0, bufs);
           else
-            walk_staged<S, R, +1, true>(c, k, A, B, q, y0, y1, it.x0, bufs);
+            walk_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, it.x0, bufs);
         }
       } else {
         if (down)
-          walk_direct<S, R, -1>(c, k, A, B, q, y0, y1);
+          walk_direct<S, R, -1, MODEL>(c, k, A, B, q, y0, y1);
         else
-          walk_direct<S, R, +1>(c, k, A, B, q, y0, y1);
+          walk_direct<S, R, +1, MODEL>(c, k, A, B, q, y0, y1);
       }
     } else {
       // the odd last step of the chunk: single two-lattice steps of the
       // segment's owned cells
       const int x = it.x0 - 1 + lane;
       if (lane >= 1 && lane <= kStripCols && x < c.nx)
-        for (int y = y0; y < y1; ++y) update_cell<S, R>(c, k, 2, x, y);
+        for (int y = y0; y < y1; ++y) update_cell<S, R, MODEL>(c, k, 2, x, y);
     }
   }
 }
 
 template <typename S, typename R, bool STAGED>
 hipError_t dispatch_batch(const CavDev *cavs, const BatchTile *items, const int32_t *hdr,
-                          int item_cap, const LaunchCfg &cfg, int launch_index, int grid,
-                          hipStream_t s) {
+                          int item_cap, int model, const LaunchCfg &cfg, int launch_index,
+                          int grid, hipStream_t s) {
   if (cfg.seg < 1 || cfg.seg > kMaxSegmentRows) return hipErrorInvalidValue;
   const int per_block = STAGED ? kStagedWaves : kDirectWaves;
   const int order = cfg.zigzag ? 4 : 0;
-  hipLaunchKernelGGL((k_step2_batch<S, R, STAGED>), dim3(grid), dim3(per_block * kWave), 0, s,
-                     cavs, items, hdr, item_cap, cfg.seg, launch_index, order);
+  with_model(model, [&](auto m) {
+    hipLaunchKernelGGL((k_step2_batch<S, R, STAGED, decltype(m)::value>), dim3(grid),
+                       dim3(per_block * kWave), 0, s, cavs, items, hdr, item_cap, cfg.seg,
+                       launch_index, order);
+    return 0;
+  });
   return hipGetLastError();
 }
 
@@ -544,19 +551,19 @@ int step2_batch_grid(int num_cus) {
 }
 
 hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
-                              const int32_t *hdr_dev, int item_cap, int precision,
+                              const int32_t *hdr_dev, int item_cap, int precision, int model,
                               const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
   if (cfg.staged)
     return precision == 0
-               ? dispatch_batch<double, double, true>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
-                                                      launch_index, grid, s)
-               : dispatch_batch<float, float, true>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
-                                                    launch_index, grid, s);
+               ? dispatch_batch<double, double, true>(cavs_dev, items_dev, hdr_dev, item_cap, model,
+                                                      cfg, launch_index, grid, s)
+               : dispatch_batch<float, float, true>(cavs_dev, items_dev, hdr_dev, item_cap, model,
+                                                    cfg, launch_index, grid, s);
   return precision == 0
-             ? dispatch_batch<double, double, false>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
-                                                     launch_index, grid, s)
-             : dispatch_batch<float, float, false>(cavs_dev, items_dev, hdr_dev, item_cap, cfg,
-                                                   launch_index, grid, s);
+             ? dispatch_batch<double, double, false>(cavs_dev, items_dev, hdr_dev, item_cap, model,
+                                                     cfg, launch_index, grid, s)
+             : dispatch_batch<float, float, false>(cavs_dev, items_dev, hdr_dev, item_cap, model,
+                                                   cfg, launch_index, grid, s);
 }
 
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {

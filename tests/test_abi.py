@@ -58,6 +58,15 @@ def test_derivation_matches_oracle(case):
     assert got.pitch % 64 == 0 and got.pitch >= case["nx"]
 
 
+@pytest.mark.parametrize("extra", [dict(solid_model=1), dict(solid_model=1, darcy_c=5.0, darcy_eps=0.3),
+                                   dict(solid_model=2)])
+def test_solid_model_constants_match_oracle(extra):
+    case = cavity(40, 20, **extra)
+    got = P.lbm_derive(P.make_case(case))
+    want = oracle.derive(oracle.case_from_dict(case))
+    assert (got.darcy_c, got.darcy_eps) == (want.darcy_c, want.darcy_eps)
+
+
 def test_literal_small_cavity_rates():
     lat = P.lbm_derive(P.make_case(small_cavity("literal")))
     assert lat.k0_g == 1.0 and lat.k2_g == 1.0
@@ -70,6 +79,8 @@ def test_literal_small_cavity_rates():
     dict(Ra=0.0), dict(Th=0.0), dict(k0_g=2.0), dict(k2_g=0.0), dict(k1_f=-1.0), dict(Cp=0.0),
     dict(heater_center=math.inf), dict(init=2, gauss_sigma=0.0),
     dict(param_mode=1, nu=0.1, alpha=0.0, latent=1.0), dict(param_mode=1, nu=0.1, alpha=0.1, latent=-1.0),
+    dict(solid_model=3), dict(solid_model=-1), dict(solid_model=1, darcy_c=-1.0),
+    dict(solid_model=1, darcy_eps=0.0), dict(solid_model=1, darcy_c=math.inf),
 ])
 def test_invalid_cases_rejected(bad):
     c = P.make_case(cavity(32, 16), **bad)
