@@ -32,10 +32,10 @@ REPORT_EVERY = 100
 # traffic), counter summary, steps per launch
 CSRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc")
 PATHS = {
-    "ab2": dict(kernel="k_step2<double,double,true>", src=("lbm_device.h", "lbm_step2.hip"),
+    "ab2": dict(kernel="k_step2<double,double,true,0>", src=("lbm_device.h", "lbm_step2.hip"),
                 traffic=os.path.join(ROOT, "profiles", "traffic_k_step2_fp64_2048x1024.md"), per_launch=2,
                 pattern="two lattices, two steps per launch, rows staged through LDS"),
-    "aa": dict(kernel="k_step<double,double,1>", src=("lbm_device.h", "lbm_step.hip"),
+    "aa": dict(kernel="k_step<double,double,1,false,0>", src=("lbm_device.h", "lbm_step.hip"),
                traffic=os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md"), per_launch=1,
                pattern="in-place A-A, one step per launch"),
 }
@@ -329,6 +329,41 @@ def heater_study(P, fo_end, precision, every_fo=0.005):
                 precision="fp64" if precision == 0 else "fp32s", series=rows)
 
 
+def solid_study(P, fo_end, precision, every_fo=0.01, n=256):
+    """Sensitivity of the melting to the readings the paper leaves open: the
+    solid-phase treatment of the flow (velocity scaled by the liquid fraction,
+    Carman-Kozeny drag, partial bounce-back) and the free rate k0 of the
+    enthalpy populations (0.6, 1.0, 1.4 with the scaled velocity).  Square
+    n x n cavity, Ra = 1e7, Pr = 6.2, Ste = 0.125, heater centred with width
+    0.5 L; all cases advance together in batched two-step launches."""
+    from btrirt_workloads import cavity
+    base = dict(cavity(n, n, Ra=1e7, Pr=6.2, Ste=0.125, heater_center=0.5, heater_width=0.5),
+                precision=precision, pattern=P.LBM_PATTERN_AB)
+    labels = ["scale k0=1", "darcy k0=1", "pbb k0=1", "scale k0=0.6", "scale k0=1.4"]
+    cases = [dict(base, solid_model=0), dict(base, solid_model=1), dict(base, solid_model=2),
+             dict(base, solid_model=0, k0_g=0.6), dict(base, solid_model=0, k0_g=1.4)]
+    lat = P.lbm_derive(P.make_case(cases[0]))
+    steps_per = max(2, 2 * int(round(every_fo * n * n / lat.alpha / 2)))
+    ctx = P.Context(device=0, max_slots=len(cases))
+    ctx.set_graph_chunk(100)
+    slots = [ctx.add(c) for c in cases]
+    rows = []
+    t0 = time.perf_counter()
+    for k in range(int(round(fo_end / every_fo))):
+        ctx.step_many(slots, [steps_per] * len(slots))
+        st = [ctx.reduce(s, allow_unstable=True) for s in slots]
+        rows.append(dict(fo=round(st[0]["fourier"], 5), step=st[0]["step"],
+                         melt_fraction=[x["melt_fraction"] for x in st], nusselt=[x["nusselt"] for x in st],
+                         finite=[x["finite"] for x in st]))
+        log(f"solid study Fo={st[0]['fourier']:.3f} phi={[round(x['melt_fraction'], 5) for x in st]} "
+            f"Nu={[round(x['nusselt'], 2) for x in st]} ({time.perf_counter() - t0:.0f} s)")
+        if not all(x["finite"] for x in st):
+            break
+    ctx.close()
+    return dict(study="solid-phase readings and k0", cases=labels, alpha=lat.alpha, steps_per_report=steps_per,
+                precision="fp64" if precision == 0 else "fp32s", series=rows)
+
+
 def calib_copy(nbytes):
     """Plain device copy of a known size, for scaling HBM counters."""
     import torch
@@ -357,8 +392,8 @@ def main():
                                        "serving_study", "two_step"],
                     default="",
                     help="run one variant alone (for profiling) and print its result")
-    ap.add_argument("--study", choices=["heater"], default="",
-                    help="run the heater-position study of the cavity section instead of the benchmark")
+    ap.add_argument("--study", choices=["heater", "solid"], default="",
+                    help="run a study instead of the benchmark: heater position (Sec. 3.2) or solid-phase readings and k0")
     ap.add_argument("--fo", type=float, default=0.1, help="study: final Fourier number")
     ap.add_argument("--precision", choices=["fp64", "fp32s"], default="fp64", help="study precision")
     args = ap.parse_args()
@@ -372,7 +407,8 @@ def main():
     import paper_1909_13086_amd as P
 
     if args.study:
-        res = heater_study(P, args.fo, 0 if args.precision == "fp64" else 1)
+        prec = 0 if args.precision == "fp64" else 1
+        res = heater_study(P, args.fo, prec) if args.study == "heater" else solid_study(P, args.fo, prec)
         print(json.dumps(res), flush=True)
         return
 
