@@ -79,6 +79,9 @@ PIN_CHECKS = [
     lambda: solid.test_darcy_velocity_is_the_mean_momentum_and_momentum_gains_the_total_force(0),
     lambda: solid.test_partial_bounce_back_mixes_free_fluid_and_full_bounce_back(0),
     lambda: solid.test_liquid_cell_is_a_free_fluid_under_every_reading(oracle.SOLID_DARCY),
+    solid.test_darcy_drag_holds_the_solid_and_grows_with_the_constant,
+    lambda: solid.test_cavity_budget_symmetry_and_still_solid_under_every_reading(oracle.SOLID_DARCY),
+    lambda: solid.test_cavity_budget_symmetry_and_still_solid_under_every_reading(oracle.SOLID_PBB),
 ]
 
 
