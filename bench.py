@@ -299,14 +299,14 @@ def heater_study(P, fo_end, precision, every_fo=0.005):
     """Heater-position study of Sec. 3.2 (the liquid-fraction curves of Fig. 3b):
     square 512x512 cavity, Ra = 1e8, Pr = 6.2, Ste = 0.125, heater width
     D = 0.5 L at centres C = 0.25, 0.375, 0.5 L, all three advanced together in
-    batched launches; melt fraction and Nusselt number every `every_fo` in
-    Fourier number up to `fo_end`."""
+    batched two-step launches on two lattices; melt fraction and Nusselt number
+    every `every_fo` in Fourier number up to `fo_end`."""
     from btrirt_workloads import cavity
     cs = [0.25, 0.375, 0.5]
     cases = [dict(cavity(512, 512, Ra=1e8, Pr=6.2, Ste=0.125, heater_center=c, heater_width=0.5),
-                  precision=precision) for c in cs]
+                  precision=precision, pattern=P.LBM_PATTERN_AB) for c in cs]
     lat = P.lbm_derive(P.make_case(cases[0]))
-    steps_per = max(1, int(round(every_fo * 512 * 512 / lat.alpha)))
+    steps_per = max(2, 2 * int(round(every_fo * 512 * 512 / lat.alpha / 2)))
     n_rep = int(round(fo_end / every_fo))
     ctx = P.Context(device=0, max_slots=3)
     ctx.set_graph_chunk(100)
