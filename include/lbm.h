@@ -245,9 +245,13 @@ int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
 int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
-/* Times the candidate tiles on a scratch cavity of the given size and
- * precision, selects the fastest and, when cache_path is not NULL, records
- * it there (JSON); a cached entry for the same size class is reused. */
+/* Times the candidates on a scratch cavity of the given size and precision
+ * and selects the fastest: block shape, rows per lane and walk flags of the
+ * one-step kernels, then segment rows and staged or direct rows of the
+ * two-step kernel (lbm_set_launch, lbm_set_fusion).  When cache_path is not
+ * NULL the choice is recorded there (JSON, one entry per precision and
+ * power-of-two size class: bx, by, cpl, flags, us per one-step launch,
+ * segment rows, us per two-step launch) and a cached entry is reused. */
 int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path);
 /* Waits for all work on the context stream. */
 int lbm_sync(lbm_ctx *c);

@@ -110,6 +110,9 @@ class Context:
     def get_fusion(self, precision):
         return L.lbm_get_fusion(self.h, precision)
 
+    def autotune(self, precision, nx, ny, cache_path=None):
+        L.lbm_autotune(self.h, precision, nx, ny, cache_path)
+
     def set_graph_chunk(self, chunk):
         L.lbm_set_graph_chunk(self.h, chunk)
 

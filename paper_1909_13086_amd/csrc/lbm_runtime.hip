@@ -1180,20 +1180,59 @@ void write_cache(const char *path, const std::map<std::string, std::vector<doubl
 
 }  // namespace
 
+namespace {
+
+// Average ms of `reps` launches after two warm-up launches; each launch flips
+// the scratch cavity's storage parity.
+template <typename Launch>
+int time_launches(lbm_ctx *c, CavDev &d, hipEvent_t e0, hipEvent_t e1, int reps, Launch launch,
+                  float *ms) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = launch(d);
+    d.parity ^= 1;
+  }
+  e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
+  for (int k = 0; k < reps && e == hipSuccess; ++k) {
+    e = launch(d);
+    d.parity ^= 1;
+  }
+  e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
+  e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+  float t = 0.0f;
+  e = e == hipSuccess ? hipEventElapsedTime(&t, e0, e1) : e;
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  *ms = t / reps;
+  return LBM_OK;
+}
+
+int flags_of(const LaunchCfg &L) {
+  return (L.xcd ? LBM_LAUNCH_XCD_BANDS : 0) | (L.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
+         (L.reverse ? LBM_LAUNCH_ALTERNATE : 0) | (L.zigzag ? LBM_LAUNCH_ZIGZAG : 0) |
+         (L.staged ? LBM_LAUNCH_STAGED : 0);
+}
+
+}  // namespace
+
 extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
   const std::string key = size_class(precision, nx, ny);
   auto cache = read_cache(cache_path);
   auto it = cache.find(key);
-  if (it != cache.end())
-    return lbm_set_launch(c, precision, (int)it->second[0], (int)it->second[1],
-                          (int)it->second[2], (int)it->second[3]);
+  if (it != cache.end()) {
+    const std::vector<double> &v = it->second;
+    int rc = lbm_set_launch(c, precision, (int)v[0], (int)v[1], (int)v[2], (int)v[3]);
+    if (rc == LBM_OK && v.size() >= 6) rc = lbm_set_fusion(c, precision, 2, (int)v[5]);
+    return rc;
+  }
+  // scratch cavity on two lattices: the one-step candidates run in place on
+  // its first lattice, the two-step candidates on both
   lbm_case cs{};
   cs.nx = nx;
   cs.ny = ny;
   cs.precision = precision;
-  cs.pattern = LBM_PATTERN_AA;
+  cs.pattern = LBM_PATTERN_AB;
   cs.param_mode = LBM_PARAM_DIMENSIONLESS;
   cs.init = LBM_INIT_SOLID_AT_TM;
   cs.Ra = 1e6; cs.Pr = 1.0; cs.Ste = 1.0; cs.Ma = 0.1;
@@ -1201,6 +1240,7 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   cs.heater_center = 0.5; cs.heater_width = 0.25;
   cs.k0_g = cs.k2_g = cs.k0_f = cs.k1_f = std::nan("");
   cs.gauss_sigma = 1.0;
+  cs.darcy_c = cs.darcy_eps = std::nan("");
   lbm_lattice lat;
   std::string why;
   if (derive(&cs, &lat, why) != LBM_OK) return fail(LBM_EINVAL, why);
@@ -1210,52 +1250,62 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
     (void)hipGetLastError();
     return fail(LBM_ENOMEM, "autotune scratch cavity does not fit");
   }
-  CavDev d = make_dev(&cs, lat, lay, base);
+  CavDev two = make_dev(&cs, lat, lay, base);
+  CavDev one = two;
+  one.pattern = LBM_PATTERN_AA;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = LBM_OK;
-  LaunchCfg best;
-  float best_ms = 1e30f;
   const LaunchCfg saved = c->launch[precision];
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-      lbm::launch_init(d, precision, LBM_INIT_SOLID_AT_TM, 0, 0, 1, c->stream) != hipSuccess ||
-      lbm::launch_fill_zero(d.cumq, lay.cumq_bytes, c->stream) != hipSuccess) {
+      lbm::launch_init(two, precision, LBM_INIT_SOLID_AT_TM, 0, 0, 1, c->stream) != hipSuccess ||
+      lbm::launch_fill_zero(two.cumq, lay.cumq_bytes, c->stream) != hipSuccess) {
     rc = fail(LBM_EDEVICE, "autotune set-up failed");
   }
+  const int reps = 10;
+  // one step per launch: block shape, rows per lane, walk flags
+  LaunchCfg best = saved;
+  float best_ms = 1e30f;
   const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
   const int cpls[] = {1, 2, 4};
-  const int reps = 10;
   for (const auto &sh : shapes) {
     for (int cpl : cpls) {
       for (int flags = 0; flags < 8 && rc == LBM_OK; ++flags) {
-        LaunchCfg cfg;
+        LaunchCfg cfg = saved;
         cfg.bx = sh[0];
         cfg.by = sh[1];
         cfg.cpl = cpl;
         cfg.xcd = flags & LBM_LAUNCH_XCD_BANDS ? 1 : 0;
         cfg.nt = flags & LBM_LAUNCH_NONTEMPORAL ? 1 : 0;
         cfg.reverse = flags & LBM_LAUNCH_ALTERNATE ? 1 : 0;
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-          e = lbm::launch_step(d, precision, cfg, c->stream);
-          d.parity ^= 1;
-        }
-        e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
-        for (int k = 0; k < reps && e == hipSuccess; ++k) {
-          e = lbm::launch_step(d, precision, cfg, c->stream);
-          d.parity ^= 1;
-        }
-        e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
-        e = e == hipSuccess ? hipEventSynchronize(e1) : e;
         float ms = 0.0f;
-        e = e == hipSuccess ? hipEventElapsedTime(&ms, e0, e1) : e;
-        if (e != hipSuccess) {
-          rc = fail(LBM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
-          break;
-        }
-        if (ms < best_ms) {
+        rc = time_launches(c, one, e0, e1, reps,
+                           [&](const CavDev &d) { return lbm::launch_step(d, precision, cfg, c->stream); },
+                           &ms);
+        if (rc == LBM_OK && ms < best_ms) {
           best_ms = ms;
           best = cfg;
         }
+      }
+    }
+  }
+  // two steps per launch: segment rows, rows staged or loaded directly
+  int best_seg = saved.seg, best_staged = saved.staged;
+  float best2_ms = 1e30f;
+  const int segs[] = {1, 2, 3, 4, 6, 8};
+  for (int seg : segs) {
+    for (int staged = 0; staged < 2 && rc == LBM_OK; ++staged) {
+      LaunchCfg cfg = best;
+      cfg.zigzag = 1;
+      cfg.seg = seg;
+      cfg.staged = staged;
+      float ms = 0.0f;
+      rc = time_launches(c, two, e0, e1, reps,
+                         [&](const CavDev &d) { return lbm::launch_step2(d, precision, cfg, c->stream); },
+                         &ms);
+      if (rc == LBM_OK && ms < best2_ms) {
+        best2_ms = ms;
+        best_seg = seg;
+        best_staged = staged;
       }
     }
   }
@@ -1267,16 +1317,17 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
     c->launch[precision] = saved;
     return rc;
   }
-  // the segment walk and row staging belong to the two-step kernel: kept
-  const int best_flags = (best.xcd ? LBM_LAUNCH_XCD_BANDS : 0) |
-                         (best.nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
-                         (best.reverse ? LBM_LAUNCH_ALTERNATE : 0) |
-                         (saved.zigzag ? LBM_LAUNCH_ZIGZAG : 0) |
-                         (saved.staged ? LBM_LAUNCH_STAGED : 0);
+  best.zigzag = 1;
+  best.staged = best_staged;
+  const int best_flags = flags_of(best);
+  // entry: bx, by, cpl, flags, us per one-step launch, segment rows, us per
+  // two-step launch
   cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best_flags,
-                1000.0 * best_ms / reps};
+                1000.0 * best_ms, (double)best_seg, 1000.0 * best2_ms};
   write_cache(cache_path, cache);
-  return lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best_flags);
+  rc = lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best_flags);
+  if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, saved.fuse, best_seg);
+  return rc;
 }
 
 // ---------------------------------------------------------------------------

@@ -136,3 +136,32 @@ def test_two_step_batch_uneven_steps_equal_solo(P, flags, seg):
         assert np.array_equal(got[k][0][0], want[0][0]) and np.array_equal(got[k][0][1], want[0][1]), k
         for key in ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "budget_residual"):
             assert got[k][1][key] == want[1][key], (k, key)
+
+
+def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path):
+    import json
+    path = str(tmp_path / "tune.json")
+    case = dict(cavity(200, 90, Ra=1e6, heater_center=0.4), pattern=P.LBM_PATTERN_AB)
+    f0, g0 = _random_state(81, 200, 90)
+    print("case autotune 200x90 FP64", flush=True)
+    with P.Context(device=0, max_slots=2) as ctx:
+        ctx.autotune(0, 200, 90, path)
+        bx, by, cpl, flags = ctx.get_launch(0)
+        fuse, seg = ctx.get_fusion(0)
+        assert bx % 64 == 0 and bx * by <= 256 and cpl in (1, 2, 4) and fuse == 2 and 1 <= seg <= 8
+        assert flags & P.LBM_LAUNCH_ZIGZAG
+        s = ctx.add(case)
+        ctx.state_load(s, f0, g0)
+        ctx.step(s, 9)
+        tuned = ctx.state_save(s)
+    entry = list(json.load(open(path)).values())
+    assert len(entry) == 1 and len(entry[0]) == 7 and entry[0][:4] == [bx, by, cpl, flags] and entry[0][5] == seg
+    with P.Context(device=0, max_slots=2) as ctx:
+        ctx.autotune(0, 200, 90, path)  # reuses the cached entry
+        assert ctx.get_launch(0) == (bx, by, cpl, flags) and ctx.get_fusion(0) == (2, seg)
+        ctx.set_fusion(0, 1)
+        s = ctx.add(case)
+        ctx.state_load(s, f0, g0)
+        ctx.step(s, 9)
+        single = ctx.state_save(s)
+    assert np.array_equal(tuned[0], single[0]) and np.array_equal(tuned[1], single[1])
