@@ -22,23 +22,29 @@ def solo_stats(P, case, steps):
         return ctx.reduce(s, allow_unstable=True)
 
 
-def _trace(P):
+def _trace(P, patterns):
     sizes = [(64, 32), (128, 64), (256, 128), (96, 48), (200, 100)]
     out = []
     for k in range(12):
         nx, ny = sizes[k % len(sizes)]
         prec = P.LBM_FP32_SHIFTED if k % 2 else P.LBM_FP64
-        case = dict(cavity(nx, ny, Ra=10 ** (5 + (k % 3)), heater_center=0.2 + 0.05 * k), precision=prec)
+        case = dict(cavity(nx, ny, Ra=10 ** (5 + (k % 3)), heater_center=0.2 + 0.05 * k), precision=prec,
+                    pattern=patterns[k % len(patterns)], solid_model=(k // 4) % 3)
         out.append((case, 1500 + 97 * k, 0.0005 * k))
     return out
 
 
-def test_served_results_equal_solo_runs(P):
+@pytest.mark.parametrize("patterns", ["aa", "ab", "mixed"])
+def test_served_results_equal_solo_runs(P, patterns):
+    """In place, on two lattices (two-step batched launches, odd remainders
+    included) and both mixed, with all three solid readings in the mix."""
     from paper_1909_13086_amd import serve
-    trace = _trace(P)
+    pat = {"aa": [P.LBM_PATTERN_AA], "ab": [P.LBM_PATTERN_AB],
+           "mixed": [P.LBM_PATTERN_AA, P.LBM_PATTERN_AB, P.LBM_PATTERN_AB]}[patterns]
+    trace = _trace(P, pat)
     fp = [P.lbm_footprint(P.make_case(c)) for c, _, _ in trace]
     budget = 4 * max(fp) + (8 << 20)  # admission binds: a few resident at a time
-    print(f"case serving 12 requests, budget {budget} bytes", flush=True)
+    print(f"case serving 12 requests ({patterns}), budget {budget} bytes", flush=True)
     with P.Context(device=0, max_slots=16, lend_memory=False) as ctx:
         ctx.set_graph_chunk(50)
         srv = serve.Server(ctx.h, budget, chunk=50)
