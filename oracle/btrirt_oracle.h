@@ -13,7 +13,10 @@
  *     g (equilibrium of Eq. (3), k1 from Eq. (4), k2 = 2 - k1 from Eq. (5)) and,
  *     as a reading of the paper, to the Boussinesq flow populations f;
  *   - Sec. 3.2: cavity with no-slip adiabatic walls and a bottom strip held at
- *     Th, the PCM starting solid at Tm.
+ *     Th, the PCM starting solid at Tm;
+ *   - how the solid holds the flow still, which the paper does not state: three
+ *     readings (velocity scaled by the liquid fraction, Carman-Kozeny drag,
+ *     partial bounce-back), see OR_SOLID_*.
  * Every reading of a point the paper leaves open is stated beside the code that
  * takes it.  Storage is two lattices with pull streaming; this is the plain
  * reference, not a fast solver.
@@ -22,7 +25,9 @@
  * invariants or independently coded special cases (moment identities of the
  * equilibria and projections, the SRT limit, the enthalpy map, the Neumann
  * (Stefan) solution of Eqs. (6)-(7), Gaussian diffusion, conservation, the
- * discrete heater budget, Poiseuille flow, mirror symmetry and quiescence).
+ * discrete heater budget, Poiseuille flow, mirror symmetry and quiescence; for
+ * the solid readings: the drag's half-step momentum balance, the bounce-back's
+ * affine mix of a free-fluid collision and a full reflection).
  * The coupled high-Rayleigh cavity itself has no printed numbers in the paper:
  * beyond those properties its trajectories are "parity unpinned".
  */
