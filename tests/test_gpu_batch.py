@@ -165,3 +165,30 @@ def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path):
         ctx.step(s, 9)
         single = ctx.state_save(s)
     assert np.array_equal(tuned[0], single[0]) and np.array_equal(tuned[1], single[1])
+
+
+@pytest.mark.parametrize("pattern", ["aa", "ab"])
+def test_full_batch_sweep_equals_solo_runs(P, pattern):
+    """The 64-cavity workload in the launch configuration the benchmark times
+    (FP32 shifted, 100-step graphs, cache groups of at most 160 MiB): every
+    cavity's diagnostics equal its solo run's bit for bit after a graph chunk
+    and an odd remainder."""
+    pat = P.LBM_PATTERN_AA if pattern == "aa" else P.LBM_PATTERN_AB
+    cases = [dict(c, precision=P.LBM_FP32_SHIFTED, pattern=pat) for c in batch_sweep()]
+    steps = 107
+    print(f"case 64-cavity sweep ({pattern}) batched vs solo, {steps} steps", flush=True)
+    with P.Context(device=0, max_slots=len(cases)) as ctx:
+        ctx.set_graph_chunk(100)
+        slots = [ctx.add(c) for c in cases]
+        ctx.step(P.LBM_ALL, steps)
+        got = [ctx.reduce(s) for s in slots]
+    keys = ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "mass", "max_u")
+    with P.Context(device=0, max_slots=1) as ctx:
+        for k, c in enumerate(cases):
+            s = ctx.add(c)
+            ctx.step(s, steps)
+            want = ctx.reduce(s)
+            ctx.release(s)
+            assert got[k]["step"] == steps
+            for key in keys:
+                assert got[k][key] == want[key], (k, key)
