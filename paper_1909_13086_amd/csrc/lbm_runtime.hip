@@ -1178,10 +1178,6 @@ void write_cache(const char *path, const std::map<std::string, std::vector<doubl
   std::rename(tmp.c_str(), path);
 }
 
-}  // namespace
-
-namespace {
-
 // Average ms of `reps` launches after two warm-up launches; each launch flips
 // the scratch cavity's storage parity.
 template <typename Launch>
