@@ -7,6 +7,8 @@
 #include "lbm.h"
 #include "lbm_internal.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -46,6 +48,44 @@ constexpr int kPitchAlign = 64;  // cells: one wavefront per row segment
 constexpr size_t kByteAlign = 256;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Named ranges for ROCm's tracer (roctx): each host call that enqueues or
+// waits for GPU work opens one, so `rocprofv3 --marker-trace` shows which
+// kernels a call issued.  The roctx library is looked up once at run time;
+// without it the ranges cost nothing.
+struct Roctx {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+};
+
+const Roctx &roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (h) {
+      x.push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+      x.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+      if (!x.push || !x.pop) x.push = nullptr, x.pop = nullptr;
+    }
+    return x;
+  }();
+  return r;
+}
+
+class TraceRange {
+ public:
+  explicit TraceRange(const char *name) : on_(roctx().push != nullptr) {
+    if (on_) roctx().push(name);
+  }
+  ~TraceRange() {
+    if (on_) roctx().pop();
+  }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+
+ private:
+  bool on_;
+};
 
 bool rate_ok(double k) { return std::isfinite(k) && k > 0.0 && k < 2.0; }
 
@@ -891,6 +931,7 @@ int lbm_release(lbm_ctx *c, int slot) {
 }
 
 int lbm_step(lbm_ctx *c, int slot, int64_t nsteps) {
+  TraceRange range("lbm_step");
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   if (nsteps == 0) return LBM_OK;
@@ -901,6 +942,7 @@ int lbm_step(lbm_ctx *c, int slot, int64_t nsteps) {
 }
 
 int lbm_step_many(lbm_ctx *c, int count, const int32_t *slots, const int64_t *nsteps) {
+  TraceRange range("lbm_step_many");
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (count < 0 || (count > 0 && (!slots || !nsteps))) return fail(LBM_EINVAL, "bad slot list");
   std::vector<int> ids(count);
@@ -924,6 +966,7 @@ int lbm_set_group_bytes(lbm_ctx *c, size_t bytes) {
 }
 
 int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out) {
+  TraceRange range("lbm_reduce");
   int rc = check_slot(c, slot);
   if (rc != LBM_OK) return rc;
   if (!out) return fail(LBM_EINVAL, "output is NULL");
@@ -938,6 +981,7 @@ int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out) {
 }
 
 int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n) {
+  TraceRange range("lbm_fields");
   int rc = check_slot(c, slot);
   if (rc != LBM_OK) return rc;
   Slot &s = c->slots[slot];
