@@ -855,6 +855,7 @@ void lbm_destroy(lbm_ctx *c) {
 
 int lbm_set_case(lbm_ctx *c, const lbm_case *cs, void *dev_buf, size_t buf_bytes,
                  int *slot_out) {
+  TraceRange range("lbm_set_case");
   if (!c || !slot_out) return fail(LBM_EINVAL, "context or slot output is NULL");
   *slot_out = -1;
   lbm_lattice lat;
