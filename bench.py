@@ -154,36 +154,39 @@ def fp32_variant(P, steps, path="ab2"):
     ctx.step(slot, 100)
     ms = time_steps(P, ctx, slot, steps)
     st = ctx.reduce(slot)
-    seg = ctx.get_fusion(P.LBM_FP32_SHIFTED)[1]
+    fuse, seg = ctx.get_fusion(P.LBM_FP32_SHIFTED)
     ctx.close()
     cells = case["nx"] * case["ny"]
     mlups = cells * steps / (ms * 1e-3) / 1e6
-    pattern = PATHS[path]["pattern"] + (f", {seg}-row segments" if path == "ab2" else "")
+    pattern = (f"two lattices, {fuse} steps per launch, rows staged through LDS, {seg}-row segments"
+               if path == "ab2" else PATHS[path]["pattern"])
     log(f"fp32s ({pattern}): {mlups:.0f} MLUPS")
     return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=pattern,
                 hbm_frac=round(mlups * 1e6 * BYTES_PER_LU[1] / (HBM_PEAK_GBS * 1e9), 4),
                 melt_fraction=st["melt_fraction"])
 
 
-def hbm_bound_variant(P, steps=200):
+def hbm_bound_variant(P, steps=240):
     """The same cavity physics on a 4096x2048 lattice, whose working set (1.2 GB
     FP64 and 604 MB FP32 in place, twice that on two lattices) is far above the
     256 MB Infinity Cache: the HBM-bound regime, in place and two-step."""
     from btrirt_workloads import large_cavity
     out = {}
-    for pattern, pname in ((P.LBM_PATTERN_AA, "in_place"), (P.LBM_PATTERN_AB, "two_step")):
+    for pattern, pname in ((P.LBM_PATTERN_AA, "in_place"), (P.LBM_PATTERN_AB, "fused")):
         for prec, name in ((0, "fp64"), (1, "fp32s")):
             case = dict(large_cavity(4096, 2048), precision=prec, pattern=pattern)
             ctx = P.Context(device=0, max_slots=1)
             slot = ctx.add(case)
-            ctx.step(slot, 10)
+            ctx.step(slot, 12)
+            fuse = ctx.get_fusion(prec)[0] if pattern == P.LBM_PATTERN_AB else 1
             ms = time_steps(P, ctx, slot, steps)
             ctx.close()
             cells = 4096 * 2048
             us = ms * 1e3 / steps
             gbs = BYTES_PER_LU[prec] * cells / (us * 1e-6) / 1e9
             out[f"{pname}_{name}"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
-                                          achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+                                          steps_per_launch=fuse, achieved_gbs=round(gbs, 1),
+                                          frac=round(gbs / HBM_PEAK_GBS, 4))
     log(f"hbm-bound 4096x2048: {out}")
     return out
 

@@ -234,24 +234,36 @@ enum {
  * Results do not depend on the tile or the flags. */
 int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags);
 int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags);
-/* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2 a
- * single launch advances a LBM_PATTERN_AB slot by two steps, reading its
- * lattice once and writing the other once (each wavefront walks a strip of
- * 62 columns up a segment of segment_rows rows, 1 to 64, keeping a
- * three-row window of first-step values in registers).  Results equal those
- * of single steps bit for bit.  Default 2 steps per launch, segments of 2 rows
- * (FP64) or 4 rows (FP32). */
+/* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2 or
+ * 3 a single launch advances a LBM_PATTERN_AB slot by that many steps,
+ * reading its lattice once and writing the other once.  Each wavefront walks
+ * a strip of 62 (two steps) or 60 (three steps) columns along a segment of
+ * segment_rows rows, 1 to 64, keeping three-row windows of the intermediate
+ * steps in registers; rows always pass through LDS in three-step launches.
+ * Segment rows are stored per depth (2 and 3); segment_rows = 0 keeps the
+ * stored value.  lbm_get_fusion returns the segment rows of the current
+ * depth.  Launches never fuse steps across a report step, and step counts
+ * that are not a multiple end with a shorter launch.  Batched launches
+ * (lbm_step_many) fuse at most two steps, with the two-step segment rows.
+ * Results equal those of single steps bit for bit.  Default: FP64 2 steps
+ * per launch, segments of 2 rows (its three-step kernel exceeds the register
+ * file and spills); FP32 3 steps per launch, segments of 6 rows (two-step
+ * segments of 4 rows).  LBM_EINVAL for steps_per_launch outside 1..3 or
+ * segment_rows outside 0..64. */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
 int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
 /* Times the candidates on a scratch cavity of the given size and precision
  * and selects the fastest: block shape, rows per lane and walk flags of the
- * one-step kernels, then segment rows and staged or direct rows of the
- * two-step kernel (lbm_set_launch, lbm_set_fusion).  When cache_path is not
- * NULL the choice is recorded there (JSON, one entry per precision and
- * power-of-two size class: bx, by, cpl, flags, us per one-step launch,
- * segment rows, us per two-step launch) and a cached entry is reused. */
+ * one-step kernels, segment rows and staged or direct rows of the two-step
+ * kernel, segment rows of the three-step kernel, and then two or three steps
+ * per launch by the time per step (unless the context runs single steps)
+ * (lbm_set_launch, lbm_set_fusion).  When cache_path is not NULL the choice is
+ * recorded there (JSON, one entry per precision and power-of-two size class:
+ * bx, by, cpl, flags, us per one-step launch, segment rows and us per launch
+ * of the two-step kernel, the same of the three-step kernel) and a cached
+ * entry is reused. */
 int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path);
 /* Waits for all work on the context stream. */
 int lbm_sync(lbm_ctx *c);

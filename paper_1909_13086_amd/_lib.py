@@ -317,9 +317,9 @@ def lbm_get_fusion(ctx, precision):
 
 
 def lbm_set_fusion(ctx, precision, steps_per_launch, segment_rows=None):
-    if segment_rows is None:
-        segment_rows = lbm_get_fusion(ctx, precision)[1]
-    _check(lib().lbm_set_fusion(ctx, int(precision), int(steps_per_launch), int(segment_rows)))
+    # None keeps the segment rows stored for that number of steps per launch
+    _check(lib().lbm_set_fusion(ctx, int(precision), int(steps_per_launch),
+                                0 if segment_rows is None else int(segment_rows)))
 
 
 def lbm_set_graph_chunk(ctx, chunk):

@@ -54,16 +54,21 @@ struct LaunchCfg {
   int reverse = 1;  // walk tiles backwards on odd storage parity
   int zigzag = 1;   // two-step kernel: odd segments walked downwards
   int staged = 1;   // two-step kernel: rows copied into LDS one row ahead
-  int fuse = 2;     // steps per launch of the two-lattice pattern (1 or 2)
+  int fuse = 2;     // steps per launch of the two-lattice pattern (1, 2 or 3)
   int seg = 4;      // rows per wavefront segment of the two-step kernel
+  int seg3 = 6;     // rows per wavefront segment of the three-step kernel
 };
 constexpr int kMaxSegmentRows = 64;
 
 // Defaults per precision, the fastest measured on MI355X at 2048x1024 and
-// 4096x2048: two-step segments of 2 rows in FP64, 4 rows in FP32.
+// 4096x2048: FP64 two steps per launch in segments of 2 rows (its three-step
+// kernel does not fit the register file), FP32 three steps per launch in
+// segments of 6 rows (two-step launches, as in the batched path, 4 rows).
 inline LaunchCfg default_launch(int precision) {
   LaunchCfg L;
+  L.fuse = precision == 0 ? 2 : 3;
   L.seg = precision == 0 ? 2 : 4;
+  L.seg3 = 6;
   return L;
 }
 
@@ -89,6 +94,8 @@ hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hip
 // Two steps of the two-lattice pattern in one launch: reads pop[parity],
 // writes pop[parity ^ 1].
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
+// Three steps per launch (two-lattice pattern), rows always staged through LDS.
+hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
 // entries (the kernel ignores a header that points outside them).
 // model: the solid model shared by every cavity of the tile list (kSolid*).

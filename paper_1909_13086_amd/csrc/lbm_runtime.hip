@@ -412,34 +412,44 @@ int enqueue_one_step(lbm_ctx *c, Slot &s) {
   return LBM_OK;
 }
 
-// Two-lattice slots may advance two steps per launch.
-bool fused(const lbm_ctx *c, const Slot &s) {
-  return s.cs.pattern == LBM_PATTERN_AB && c->launch[s.cs.precision].fuse == 2;
+// Steps per launch of a slot: two-lattice slots may advance two or three
+// steps per launch, in-place slots one.
+int steps_per_launch(const lbm_ctx *c, const Slot &s) {
+  return s.cs.pattern == LBM_PATTERN_AB ? c->launch[s.cs.precision].fuse : 1;
 }
 
-int enqueue_two_steps(lbm_ctx *c, Slot &s) {
-  HIP_TRY(lbm::launch_step2(s.dev, s.cs.precision, c->launch[s.cs.precision], c->stream));
-  s.dev.parity ^= 1;  // the state moved to the other lattice
-  s.step += 2;
+// Slots that the batched launch advances two steps per launch (the batched
+// kernel fuses at most two).
+bool fused(const lbm_ctx *c, const Slot &s) { return steps_per_launch(c, s) >= 2; }
+
+// One launch advancing the state by m steps (1, 2 or 3, at most the slot's
+// steps per launch).  Every launch moves the state to the other lattice of a
+// two-lattice slot; in place it flips the A-A parity.
+hipError_t launch_steps(const lbm_ctx *c, const Slot &s, const CavDev &d, int m) {
+  const LaunchCfg &L = c->launch[s.cs.precision];
+  if (m == 3) return lbm::launch_step3(d, s.cs.precision, L, c->stream);
+  if (m == 2) return lbm::launch_step2(d, s.cs.precision, L, c->stream);
+  return lbm::launch_step(d, s.cs.precision, L, c->stream);
+}
+
+int enqueue_steps(lbm_ctx *c, Slot &s, int m) {
+  HIP_TRY(launch_steps(c, s, s.dev, m));
+  s.dev.parity ^= 1;
+  s.step += m;
   return LBM_OK;
 }
 
-// Launches of a chunk of n steps starting from parity p: the fused kernel
-// takes pairs, a single step finishes an odd count.  Returns the storage
-// parity after the chunk.
+// Launches of a chunk of n steps starting from parity p: launches of the
+// slot's steps per launch, then one shorter launch for the rest.  Returns the
+// storage parity after the chunk.
 int enqueue_chunk(lbm_ctx *c, const Slot &s, CavDev d, int n, hipError_t *err) {
-  const LaunchCfg &L = c->launch[s.cs.precision];
+  const int F = steps_per_launch(c, s);
   *err = hipSuccess;
-  int k = 0;
-  if (fused(c, s)) {
-    for (; k + 2 <= n && *err == hipSuccess; k += 2) {
-      *err = lbm::launch_step2(d, s.cs.precision, L, c->stream);
-      d.parity ^= 1;
-    }
-  }
-  for (; k < n && *err == hipSuccess; ++k) {
-    *err = lbm::launch_step(d, s.cs.precision, L, c->stream);
+  for (int k = 0; k < n && *err == hipSuccess;) {
+    const int m = std::min(F, n - k);
+    *err = launch_steps(c, s, d, m);
     d.parity ^= 1;
+    k += m;
   }
   return d.parity;
 }
@@ -500,12 +510,11 @@ int step_slot(lbm_ctx *c, Slot &s, int64_t n) {
       s.step += chunk;
       s.dev.parity = s.graph_after[p];
       n -= chunk;
-    } else if (fused(c, s) && n >= 2 && next != s.step + 1) {
-      rc = enqueue_two_steps(c, s);
-      n -= 2;
     } else {
-      rc = enqueue_one_step(c, s);
-      n -= 1;
+      // as many fused steps as fit before the next report
+      const int64_t m = std::min<int64_t>({(int64_t)steps_per_launch(c, s), n, next - s.step});
+      rc = m >= 2 ? enqueue_steps(c, s, (int)m) : enqueue_one_step(c, s);
+      n -= m >= 2 ? m : 1;
     }
     if (rc != LBM_OK) return rc;
     rc = record_report(c, s);
@@ -1115,11 +1124,12 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
-  if ((steps_per_launch != 1 && steps_per_launch != 2) || segment_rows < 1 ||
+  if (steps_per_launch < 1 || steps_per_launch > 3 || segment_rows < 0 ||
       segment_rows > lbm::kMaxSegmentRows)
-    return fail(LBM_EINVAL, "steps per launch in {1, 2}, segment rows in 1..64");
-  c->launch[precision].fuse = steps_per_launch;
-  c->launch[precision].seg = segment_rows;
+    return fail(LBM_EINVAL, "steps per launch in {1, 2, 3}, segment rows in 0..64");
+  LaunchCfg &L = c->launch[precision];
+  L.fuse = steps_per_launch;
+  if (segment_rows > 0) (steps_per_launch == 3 ? L.seg3 : L.seg) = segment_rows;
   for (auto &s : c->slots) drop_graphs(s);
   c->batch.dirty = true;  // item lists depend on the fusion
   drop_batch_graph(c);
@@ -1129,8 +1139,9 @@ int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows) {
   if (!c || !steps_per_launch || !segment_rows) return fail(LBM_EINVAL, "NULL argument");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
-  *steps_per_launch = c->launch[precision].fuse;
-  *segment_rows = c->launch[precision].seg;
+  const LaunchCfg &L = c->launch[precision];
+  *steps_per_launch = L.fuse;
+  *segment_rows = L.fuse == 3 ? L.seg3 : L.seg;
   return LBM_OK;
 }
 
@@ -1261,10 +1272,18 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   const std::string key = size_class(precision, nx, ny);
   auto cache = read_cache(cache_path);
   auto it = cache.find(key);
-  if (it != cache.end()) {
+  // entries without the three-step timing (an older format) are tuned again
+  if (it != cache.end() && it->second.size() >= 9) {
     const std::vector<double> &v = it->second;
+    const int fuse = c->launch[precision].fuse;
     int rc = lbm_set_launch(c, precision, (int)v[0], (int)v[1], (int)v[2], (int)v[3]);
-    if (rc == LBM_OK && v.size() >= 6) rc = lbm_set_fusion(c, precision, 2, (int)v[5]);
+    if (rc == LBM_OK) {
+      // the faster of two and three steps per launch, per step, unless the
+      // caller runs single steps
+      rc = lbm_set_fusion(c, precision, 2, (int)v[5]);
+      if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, 3, (int)v[7]);
+      if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, fuse == 1 ? 1 : (v[8] / 3 < v[6] / 2 ? 3 : 2), 0);
+    }
     return rc;
   }
   // scratch cavity on two lattices: the one-step candidates run in place on
@@ -1350,6 +1369,24 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
       }
     }
   }
+  // three steps per launch: segment rows (rows always staged)
+  int best_seg3 = saved.seg3;
+  float best3_ms = 1e30f;
+  const int segs3[] = {2, 4, 6, 8, 12};
+  for (int seg : segs3) {
+    if (rc != LBM_OK) break;
+    LaunchCfg cfg = best;
+    cfg.zigzag = 1;
+    cfg.seg3 = seg;
+    float ms = 0.0f;
+    rc = time_launches(c, two, e0, e1, reps,
+                       [&](const CavDev &d) { return lbm::launch_step3(d, precision, cfg, c->stream); },
+                       &ms);
+    if (rc == LBM_OK && ms < best3_ms) {
+      best3_ms = ms;
+      best_seg3 = seg;
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(c->stream);
@@ -1361,13 +1398,17 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   best.zigzag = 1;
   best.staged = best_staged;
   const int best_flags = flags_of(best);
-  // entry: bx, by, cpl, flags, us per one-step launch, segment rows, us per
-  // two-step launch
+  // entry: bx, by, cpl, flags, us per one-step launch, segment rows and us
+  // per launch of the two-step kernel, the same of the three-step kernel
   cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best_flags,
-                1000.0 * best_ms, (double)best_seg, 1000.0 * best2_ms};
+                1000.0 * best_ms, (double)best_seg, 1000.0 * best2_ms, (double)best_seg3,
+                1000.0 * best3_ms};
   write_cache(cache_path, cache);
   rc = lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best_flags);
-  if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, saved.fuse, best_seg);
+  if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, 2, best_seg);
+  if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, 3, best_seg3);
+  if (rc == LBM_OK)
+    rc = lbm_set_fusion(c, precision, saved.fuse == 1 ? 1 : (best3_ms / 3 < best2_ms / 2 ? 3 : 2), 0);
   return rc;
 }
 

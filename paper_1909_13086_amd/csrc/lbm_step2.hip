@@ -31,7 +31,8 @@ namespace {
 
 using namespace dev;
 
-constexpr int kStripCols = kWave - 2;  // owned columns per wavefront
+constexpr int kStripCols = kWave - 2;  // owned columns per wavefront (two steps)
+constexpr int kStrip3Cols = kWave - 4; // owned columns per wavefront (three steps)
 constexpr int kDirectWaves = 4;        // wavefronts per workgroup, direct rows
 constexpr int kStagedWaves = 2;        // wavefronts per workgroup, staged rows
 
@@ -70,35 +71,49 @@ __device__ __forceinline__ R lane_from(R v, int dx) {
 
 // Column of one lane of a strip.
 struct Col {
-  int x, xw;          // column (-1 .. nx) and its periodic wrap
+  int x, xw;          // column (-H .. nx+H-1) and its periodic wrap
   bool real;          // the column exists (owners, and halo columns that wrap)
   bool owner;         // lanes 1 .. 62 inside the cavity
   bool bottom_hot;    // heated column of a non-periodic bottom wall
   bool strip_flux;    // counts the first-step strip flux of row 0
 };
 
+// Halo columns and rows lie at most H cells outside the cavity (H = 1 for
+// two steps per launch, 2 for three).  With periodic sides they wrap, at
+// most H times for a cavity narrower than H.
+template <int H>
+__device__ __forceinline__ int wrap_near(int v, int n) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) v = v < 0 ? v + n : (v >= n ? v - n : v);
+  return v;
+}
+template <int H = 1>
 __device__ __forceinline__ bool col_real(const CavDev &c, int x) {
-  // only columns -1 .. nx matter (owners are 0 .. nx-1); with periodic sides
-  // the halo columns -1 and nx wrap once
-  return (x >= 0 && x < c.nx) || (c.periodic_x && (x == -1 || x == c.nx));
+  return (x >= 0 && x < c.nx) || (c.periodic_x && x >= -H && x < c.nx + H);
 }
+template <int H = 1>
 __device__ __forceinline__ int col_wrap(const CavDev &c, int x) {
-  return x < 0 ? x + c.nx : (x >= c.nx ? x - c.nx : x);
+  return wrap_near<H>(x, c.nx);
 }
+template <int H = 1>
 __device__ __forceinline__ bool row_real(const CavDev &c, int r) {
-  return (r >= 0 && r < c.ny) || (c.periodic_y && (r == -1 || r == c.ny));
+  return (r >= 0 && r < c.ny) || (c.periodic_y && r >= -H && r < c.ny + H);
 }
+template <int H = 1>
 __device__ __forceinline__ int row_wrap(const CavDev &c, int r) {
-  return r < 0 ? r + c.ny : (r >= c.ny ? r - c.ny : r);
+  return wrap_near<H>(r, c.ny);
 }
 
+// H: halo columns on each side of the strip (one per step after the first)
+template <int H = 1>
 __device__ __forceinline__ Col make_col(const CavDev &c, int x, int lane, int y0) {
   Col q;
   q.x = x;
-  q.real = col_real(c, x);
-  q.xw = col_wrap(c, x);
-  q.owner = lane >= 1 && lane <= kStripCols && x < c.nx;
-  q.bottom_hot = !c.periodic_y && x >= c.hlo && x <= c.hhi;
+  q.real = col_real<H>(c, x);
+  q.xw = col_wrap<H>(c, x);
+  q.owner = lane >= H && lane < kWave - H && x < c.nx;
+  // a halo column across a periodic side is heated as the column it wraps to
+  q.bottom_hot = !c.periodic_y && q.xw >= c.hlo && q.xw <= c.hhi;
   // the segment that owns row 0 computes that row's first step exactly once
   q.strip_flux = q.owner && q.bottom_hot && y0 == 0;
   return q;
@@ -203,10 +218,12 @@ __device__ __forceinline__ void emit(const CavDev &c, const Coef<R> &k, S *__res
   }
 }
 
-// No cell of the strip segment [x0, x0 + 62) x [y0, y1) or of its neighbours
-// lies on or beyond a wall or a periodic seam.
+// No cell within H cells of the strip segment [x0, x0 + 64 - 2H) x [y0, y1)
+// lies on or beyond a wall or a periodic seam, so no link of a cell whose
+// collision feeds an owned cell crosses one.
+template <int H = 1>
 __device__ __forceinline__ bool interior_segment(const CavDev &c, int x0, int y0, int y1) {
-  return x0 >= 1 && x0 + kStripCols + 1 <= c.nx && y0 >= 1 && y1 + 1 <= c.ny;
+  return x0 >= H && x0 + (kWave - 2 * H) + H <= c.nx && y0 >= H && y1 + H <= c.ny;
 }
 
 // Window slide: (a, c) <- (populations of c moving along D, n).
@@ -288,15 +305,16 @@ struct CopyLanes {
   uint32_t off[2];  // byte offset of the copied word within the row
 };
 
-template <typename S>
-__device__ __forceinline__ CopyLanes copy_lanes(const CavDev &c, int x0, int lane) {
+// xa: column of lane 0
+template <typename S, int H = 1>
+__device__ __forceinline__ CopyLanes copy_lanes(const CavDev &c, int xa, int lane) {
   CopyLanes L;
   const uint32_t sub = sizeof(S) == 8 ? 4u * (lane & 1) : 0u;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int m = sizeof(S) == 8 ? h * (kWave / 2) + (lane >> 1) : lane;
-    const int x = x0 - 1 + m;
-    const uint32_t e = col_real(c, x) ? (uint32_t)cell_base(c, col_wrap(c, x), 0) : 0u;
+    const int x = xa + m;
+    const uint32_t e = col_real<H>(c, x) ? (uint32_t)cell_base(c, col_wrap<H>(c, x), 0) : 0u;
     L.off[h] = e * (uint32_t)sizeof(S) + sub;
   }
   return L;
@@ -328,10 +346,10 @@ __device__ __forceinline__ void copy_planes(const char *base, const CopyLanes &L
 }
 
 // Issue the copy of row r of A into an LDS buffer of kPlanes x kWave values.
-template <typename S>
+template <typename S, int H = 1>
 __device__ __forceinline__ void copy_row(const CavDev &c, const S *__restrict__ A, const CopyLanes &L,
                                          int r, S *buf) {
-  const int64_t row = (int64_t)row_wrap(c, r) * (c.pitch >> 6) * (kPlanes * kWave);
+  const int64_t row = (int64_t)row_wrap<H>(c, r) * (c.pitch >> 6) * (kPlanes * kWave);
   const char *base = reinterpret_cast<const char *>(A + row);
   asm volatile("" ::: "memory");
   copy_planes<S>(base, L, buf, std::make_integer_sequence<int, kPlanes>{});
@@ -357,7 +375,7 @@ __device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, c
                                             S *__restrict__ B, const Col &q, int y0, int y1, int x0,
                                             S *bufs) {
   const int lane = threadIdx.x & (kWave - 1);
-  const CopyLanes L = copy_lanes<S>(c, x0, lane);
+  const CopyLanes L = copy_lanes<S>(c, x0 - 1, lane);
   auto buf = [&](int b) { return bufs + b * (kPlanes * kWave); };
   auto issue = [&](int r, int b) {
     if (row_real(c, r)) copy_row<S>(c, A, L, r, buf(b));
@@ -455,6 +473,140 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   with_model(c.solid_model, [&](auto m) {
     hipLaunchKernelGGL((k_step2<S, R, STAGED, decltype(m)::value>), grid, dim3(per_block * kWave), 0,
                        s, c, strips_x, nseg, cfg.seg, order);
+    return 0;
+  });
+  return hipGetLastError();
+}
+
+// ---- three steps per launch ---------------------------------------------
+//
+// The same scheme one level deeper: a wavefront owns 60 columns (lanes
+// 2 .. 61) of `seg` rows and walks them with two windows.  Rows are loaded
+// (staged through LDS as above) and collided once (level 1) for the rows
+// y0-2 .. y1+1; the level-1 window feeds the second step (level 2) of rows
+// y0-1 .. y1, whose window feeds the third step (level 3) of the owned rows,
+// which is stored.  Level 2 runs on every lane; only lanes 1 .. 62 hold
+// correct values there, which is all level 3 of the owned lanes reads.  Rows
+// outside the cavity give values that no owned cell uses (their links are
+// reflected at the wall).  Each level is the single-step update, so a launch
+// equals three single two-lattice steps bit for bit.
+//
+// Iteration y of the walk (direction D) computes level 1 of row y+2D, level 2
+// of row y+D and level 3 of row y, then slides both windows by one row.
+template <typename S, typename R, int D, bool WALLS, int MODEL>
+__device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+                                             S *__restrict__ B, const Col &q, int y0, int y1, int x0,
+                                             S *bufs) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const CopyLanes L = copy_lanes<S, 2>(c, x0 - 2, lane);
+  auto buf = [&](int b) { return bufs + b * (kPlanes * kWave); };
+  auto issue = [&](int r, int b) {
+    if (row_real<2>(c, r)) copy_row<S, 2>(c, A, L, r, buf(b));
+  };
+  auto level1 = [&](int r, int b, R (&f)[kQ], R (&g)[kQ]) {
+    if (!(row_real<2>(c, r) && q.real)) {
+      zero_row(f, g);
+      return;
+    }
+    read_row<S, R>(buf(b), lane, f, g);
+    first_collide<R, MODEL>(c, k, q, r, f, g);
+  };
+  // level 2 of row r into (f, g), with the strip flux of row 0 (the segment
+  // that owns row 0 computes its level 2 exactly once)
+  auto level2 = [&](int r, const R (&cf)[kQ], const R (&cg)[kQ], const R (&nf)[kQ],
+                    const R (&ng)[kQ], const R (&af)[3], const R (&ag)[3], R (&f)[kQ], R (&g)[kQ]) {
+    second_collide<R, D, WALLS, MODEL>(c, k, q, r, cf, cg, nf, ng, af, ag, f, g);
+    if (r == 0 && q.strip_flux) add_strip_flux<R>(c, k, q.x, g);
+  };
+
+  const int ys = D > 0 ? y0 : y1 - 1;
+  const int ye = D > 0 ? y1 : y0 - 1;
+  R c1f[kQ], c1g[kQ], n1f[kQ], n1g[kQ], a1f[3], a1g[3];  // level-1 window
+  R c2f[kQ], c2g[kQ], n2f[kQ], n2g[kQ], a2f[3], a2g[3];  // level-2 window
+  // prologue: level 1 of rows ys-2D .. ys+D, level 2 of rows ys-D and ys
+  issue(ys - 2 * D, 0);
+  issue(ys - D, 1);
+  wait_vm();
+  level1(ys - 2 * D, 0, c1f, c1g);
+  wait_lgkm();
+  issue(ys, 0);
+  level1(ys - D, 1, n1f, n1g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  wait_lgkm();
+  issue(ys + D, 1);
+  level1(ys, 0, n1f, n1g);
+  level2(ys - D, c1f, c1g, n1f, n1g, a1f, a1g, c2f, c2g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  wait_lgkm();
+  issue(ys + 2 * D, 0);
+  level1(ys + D, 1, n1f, n1g);
+  level2(ys, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+  slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  int b = 0;
+  for (int y = ys; y != ye; y += D, b ^= 1) {
+    // row y+2D is in buffer b; buffer b^1 (row y+D) has been read
+    wait_lgkm();
+    if (y + D != ye) issue(y + 3 * D, b ^ 1);
+    level1(y + 2 * D, b, n1f, n1g);
+    level2(y + D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+    R pf[kQ], pg[kQ];
+    second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
+    wait_vm();
+    emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+    slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
+    slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  }
+}
+
+template <typename S, typename R, int MODEL>
+__global__ __launch_bounds__(kStagedWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int nseg, int seg_rows,
+                                                     int order) {
+  __shared__ S lds[kStagedWaves * 2 * kPlanes * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
+  const int w = b * kStagedWaves + wid;
+  if (w >= strips_x * nseg) return;  // uniform per wavefront; no barriers follow
+  const int strip = w % strips_x, seg = w / strips_x;
+  const int x0 = strip * kStrip3Cols;
+  const int y0 = seg * seg_rows;
+  const int y1 = min(y0 + seg_rows, c.ny);
+  const Col q = make_col<2>(c, x0 - 2 + lane, lane, y0);
+  const Coef<R> k(c);
+  const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
+  S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
+  const bool down = (order & 4) && (seg & 1);
+  S *bufs = lds + wid * 2 * kPlanes * kWave;
+  const bool inner = interior_segment<2>(c, x0, y0, y1);
+  if (down) {
+    if (inner)
+      walk3_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+    else
+      walk3_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+  } else {
+    if (inner)
+      walk3_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+    else
+      walk3_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+  }
+}
+
+template <typename S, typename R>
+hipError_t dispatch3(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
+  if (cfg.seg3 < 1 || cfg.seg3 > kMaxSegmentRows) return hipErrorInvalidValue;
+  const int strips_x = (c.nx + kStrip3Cols - 1) / kStrip3Cols;
+  const int nseg = (c.ny + cfg.seg3 - 1) / cfg.seg3;
+  const int waves = strips_x * nseg;
+  const dim3 grid((waves + kStagedWaves - 1) / kStagedWaves);
+  const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
+  with_model(c.solid_model, [&](auto m) {
+    hipLaunchKernelGGL((k_step3<S, R, decltype(m)::value>), grid, dim3(kStagedWaves * kWave), 0, s, c,
+                       strips_x, nseg, cfg.seg3, order);
     return 0;
   });
   return hipGetLastError();
@@ -564,6 +716,10 @@ hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev
                                                      cfg, launch_index, grid, s)
              : dispatch_batch<float, float, false>(cavs_dev, items_dev, hdr_dev, item_cap, model,
                                                    cfg, launch_index, grid, s);
+}
+
+hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {
+  return precision == 0 ? dispatch3<double, double>(c, cfg, s) : dispatch3<float, float>(c, cfg, s);
 }
 
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {

@@ -148,17 +148,19 @@ def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path):
         ctx.autotune(0, 200, 90, path)
         bx, by, cpl, flags = ctx.get_launch(0)
         fuse, seg = ctx.get_fusion(0)
-        assert bx % 64 == 0 and bx * by <= 256 and cpl in (1, 2, 4) and fuse == 2 and 1 <= seg <= 8
+        assert bx % 64 == 0 and bx * by <= 256 and cpl in (1, 2, 4) and fuse in (2, 3) and 1 <= seg <= 12
         assert flags & P.LBM_LAUNCH_ZIGZAG
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)
         ctx.step(s, 9)
         tuned = ctx.state_save(s)
     entry = list(json.load(open(path)).values())
-    assert len(entry) == 1 and len(entry[0]) == 7 and entry[0][:4] == [bx, by, cpl, flags] and entry[0][5] == seg
+    assert len(entry) == 1 and len(entry[0]) == 9 and entry[0][:4] == [bx, by, cpl, flags]
+    e = entry[0]
+    assert fuse == (3 if e[8] / 3 < e[6] / 2 else 2) and seg == (e[7] if fuse == 3 else e[5])
     with P.Context(device=0, max_slots=2) as ctx:
         ctx.autotune(0, 200, 90, path)  # reuses the cached entry
-        assert ctx.get_launch(0) == (bx, by, cpl, flags) and ctx.get_fusion(0) == (2, seg)
+        assert ctx.get_launch(0) == (bx, by, cpl, flags) and ctx.get_fusion(0) == (fuse, seg)
         ctx.set_fusion(0, 1)
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)

@@ -62,16 +62,16 @@ def test_fp32_shifted_short_run_tracks_oracle(P):
     assert np.max(np.abs(gg - go)) <= 2e-6
 
 
-def test_fp32_two_step_full_size_tracks_oracle(P):
+def test_fp32_fused_full_size_tracks_oracle(P):
     """The FP32-shifted variant at the benchmark's size and launch
-    configuration (2048x1024, two lattices, two steps per launch, default
+    configuration (2048x1024, two lattices, three steps per launch, default
     segments) from a random state, against the FP64 oracle."""
     from btrirt_workloads import large_cavity
     case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED, pattern=P.LBM_PATTERN_AB)
     f0, g0 = _random_state(29, 2048, 1024)
-    print("case 2048x1024 FP32 two-step, 6 steps vs oracle", flush=True)
+    print("case 2048x1024 FP32 three-step, 6 steps vs oracle", flush=True)
     with P.Context(device=0, max_slots=1) as ctx:
-        assert ctx.get_fusion(1)[0] == 2
+        assert ctx.get_fusion(1) == (3, 6)
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)
         ctx.step(s, 6)

@@ -262,7 +262,7 @@ def test_two_step_kernel_equals_single_steps(P, geom, prec, seg, steps):
     # single steps, two-step launches with the zigzag segment walk (default)
     # and with every segment walked upwards, rows loaded directly or staged
     for fuse, flags in ((1, P.LBM_LAUNCH_DEFAULT), (2, P.LBM_LAUNCH_DEFAULT), (2, 5), (2, 5 | P.LBM_LAUNCH_STAGED),
-                        (2, 13 | P.LBM_LAUNCH_STAGED)):
+                        (2, 13 | P.LBM_LAUNCH_STAGED), (3, P.LBM_LAUNCH_DEFAULT), (3, 5 | P.LBM_LAUNCH_STAGED)):
         with P.Context(device=0, max_slots=1) as ctx:
             ctx.set_fusion(prec, fuse, seg)
             ctx.set_launch(prec, 256, 1, 1, flags)
@@ -282,7 +282,7 @@ def test_two_step_kernel_in_graphs_and_with_reports(P, chunk):
     case = dict(small_cavity("distinct"), pattern=P.LBM_PATTERN_AB)
     f0, g0 = _random_state(31, 128, 64)
     res = []
-    for fuse in (1, 2):
+    for fuse in (1, 2, 3):
         with P.Context(device=0, max_slots=1) as ctx:
             ctx.set_fusion(0, fuse, 16)
             ctx.set_graph_chunk(chunk)
@@ -291,10 +291,11 @@ def test_two_step_kernel_in_graphs_and_with_reports(P, chunk):
             ctx.set_report(s, 5, 64)
             ctx.step(s, 53)
             res.append((ctx.state_save(s), ctx.series(s)))
-    (a, sa), (b, sb) = res
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    assert [e["step"] for e in sa] == [e["step"] for e in sb] == list(range(5, 53, 5))
-    assert all(x["total_H"] == y["total_H"] for x, y in zip(sa, sb))
+    (a, sa) = res[0]
+    for b, sb in res[1:]:
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert [e["step"] for e in sa] == [e["step"] for e in sb] == list(range(5, 53, 5))
+        assert all(x["total_H"] == y["total_H"] for x, y in zip(sa, sb))
 
 
 def test_two_step_kernel_full_size_matches_oracle(P):
