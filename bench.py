@@ -32,6 +32,9 @@ REPORT_EVERY = 100
 # traffic), counter summary, steps per launch
 CSRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc")
 PATHS = {
+    "ab": dict(kernel="k_step3<double,double,0>", src=("lbm_device.h", "lbm_step2.hip"),
+               traffic=os.path.join(ROOT, "profiles", "traffic_k_step3_fp64_2048x1024.md"), per_launch=3,
+               pattern="two lattices, three steps per launch, level-2 window in LDS"),
     "ab2": dict(kernel="k_step2<double,double,true,0>", src=("lbm_device.h", "lbm_step2.hip"),
                 traffic=os.path.join(ROOT, "profiles", "traffic_k_step2_fp64_2048x1024.md"), per_launch=2,
                 pattern="two lattices, two steps per launch, rows staged through LDS"),
@@ -88,15 +91,18 @@ def time_steps(P, ctx, slot, steps, events=True):
 
 
 def run_cavity(P, path, steps, warmup, report_every=REPORT_EVERY, graph_chunk=0, tile=""):
-    """The 2048x1024 FP64 cavity on a path ("ab2" or "aa"): `warmup` steps,
-    then `steps` timed steps with diagnostics every `report_every`, then a
-    kernel-only timing of whole launches."""
+    """The 2048x1024 FP64 cavity on a path ("ab", "ab2" or "aa"): `warmup`
+    steps, then `steps` timed steps with diagnostics every `report_every`,
+    then a kernel-only timing of whole launches."""
     from btrirt_workloads import large_cavity
     import torch
 
-    case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB if path == "ab2" else P.LBM_PATTERN_AA)
+    per = PATHS[path]["per_launch"]
+    case = dict(large_cavity(), pattern=P.LBM_PATTERN_AA if path == "aa" else P.LBM_PATTERN_AB)
     cells = case["nx"] * case["ny"]
     ctx = P.Context(device=0, max_slots=2)
+    if path != "aa":
+        ctx.set_fusion(0, per)
     if graph_chunk:
         ctx.set_graph_chunk(graph_chunk)
     if tile:
@@ -117,12 +123,11 @@ def run_cavity(P, path, steps, warmup, report_every=REPORT_EVERY, graph_chunk=0,
     series = ctx.series(slot) if report_every else []
     # live time of the step kernel alone (whole launches, no diagnostics)
     slot2 = ctx.add(case)
-    k2 = 2 * max(100, min(1000, steps // 2))
+    k2 = per * max(100, min(1000, steps // per))
     ctx.step(slot2, 20)
     kms = time_steps(P, ctx, slot2, k2)
     ctx.close()
-    per = PATHS[path]["per_launch"]
-    pattern = PATHS[path]["pattern"] + (f", {seg}-row segments" if path == "ab2" else "")
+    pattern = PATHS[path]["pattern"] + (f", {seg}-row segments" if path != "aa" else "")
     return dict(case=case, cells=cells, ms=ms, wall=wall, stats=st, series=series, pattern=pattern,
                 launch_ms=kms / k2 * per, launches=k2 // per, steps_per_launch=per)
 
@@ -145,11 +150,13 @@ def in_place_variant(P, steps):
                 melt_fraction=m["stats"]["melt_fraction"])
 
 
-def fp32_variant(P, steps, path="ab2"):
+def fp32_variant(P, steps, path="ab"):
     from btrirt_workloads import large_cavity
     case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED,
-                pattern=P.LBM_PATTERN_AB if path == "ab2" else P.LBM_PATTERN_AA)
+                pattern=P.LBM_PATTERN_AA if path == "aa" else P.LBM_PATTERN_AB)
     ctx = P.Context(device=0, max_slots=1)
+    if path != "aa":
+        ctx.set_fusion(P.LBM_FP32_SHIFTED, PATHS[path]["per_launch"])
     slot = ctx.add(case)
     ctx.step(slot, 100)
     ms = time_steps(P, ctx, slot, steps)
@@ -159,7 +166,7 @@ def fp32_variant(P, steps, path="ab2"):
     cells = case["nx"] * case["ny"]
     mlups = cells * steps / (ms * 1e-3) / 1e6
     pattern = (f"two lattices, {fuse} steps per launch, rows staged through LDS, {seg}-row segments"
-               if path == "ab2" else PATHS[path]["pattern"])
+               if path != "aa" else PATHS[path]["pattern"])
     log(f"fp32s ({pattern}): {mlups:.0f} MLUPS")
     return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=pattern,
                 hbm_frac=round(mlups * 1e6 * BYTES_PER_LU[1] / (HBM_PEAK_GBS * 1e9), 4),
@@ -191,26 +198,28 @@ def hbm_bound_variant(P, steps=240):
     return out
 
 
-def two_step_variant(P, steps=400):
-    """The same cavity on the two-lattice pattern with the two-step
-    (temporally blocked) kernel: each launch reads one lattice once and writes
-    the other once for two time steps."""
+def fused_sizes_variant(P, steps=480):
+    """The same cavity on the two-lattice pattern with two and three steps per
+    launch (temporal blocking: each launch reads one lattice once and writes
+    the other once) at 2048x1024 and 4096x2048, FP64."""
     from btrirt_workloads import large_cavity
     out = {}
-    for nx, ny in ((2048, 1024), (4096, 2048)):
-        case = dict(large_cavity(nx, ny), pattern=P.LBM_PATTERN_AB)
-        ctx = P.Context(device=0, max_slots=1)
-        slot = ctx.add(case)
-        ctx.step(slot, 10)
-        ms = time_steps(P, ctx, slot, steps)
-        ctx.close()
-        us = ms * 1e3 / steps
-        cells = nx * ny
-        gbs = 2 * BYTES_PER_LU[0] * cells / (2 * us * 1e-6) / 1e9
-        out[f"{nx}x{ny}"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
-                                 us_per_launch=round(2 * us, 2),
-                                 achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
-    log(f"two-step two-lattice FP64: {out}")
+    for fuse in (2, 3):
+        for nx, ny in ((2048, 1024), (4096, 2048)):
+            case = dict(large_cavity(nx, ny), pattern=P.LBM_PATTERN_AB)
+            ctx = P.Context(device=0, max_slots=1)
+            ctx.set_fusion(0, fuse)
+            slot = ctx.add(case)
+            ctx.step(slot, 12)
+            ms = time_steps(P, ctx, slot, steps)
+            ctx.close()
+            us = ms * 1e3 / steps
+            cells = nx * ny
+            gbs = BYTES_PER_LU[0] * cells / (us * 1e-6) / 1e9
+            out[f"{nx}x{ny}_{fuse}step"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
+                                                us_per_launch=round(fuse * us, 2),
+                                                achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    log(f"fused two-lattice FP64: {out}")
     return out
 
 
@@ -395,8 +404,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--path", choices=["ab2", "aa"], default="ab2",
-                    help="ab2: two lattices, two steps per launch (default); aa: in place, one step per launch")
+    ap.add_argument("--path", choices=["ab", "ab2", "aa"], default="ab",
+                    help="ab: two lattices, three steps per launch (default); ab2: two lattices, two steps "
+                         "per launch; aa: in place, one step per launch")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--tile", default="", help="bx,by,cpl,flags for the FP64 step kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -404,7 +414,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
     ap.add_argument("--only", choices=["fp32", "batched", "batched_two_step", "serving", "serving_two_step",
-                                       "serving_study", "two_step"],
+                                       "serving_study", "sizes"],
                     default="",
                     help="run one variant alone (for profiling) and print its result")
     ap.add_argument("--study", choices=["heater", "solid"], default="",
@@ -434,10 +444,10 @@ def main():
             res = batched_variant(P, args.steps)
         elif args.only == "batched_two_step":
             res = batched_variant(P, args.steps, pattern=P.LBM_PATTERN_AB)
-        elif args.only == "two_step":
-            res = two_step_variant(P, args.steps)
+        elif args.only == "sizes":
+            res = fused_sizes_variant(P, args.steps)
         elif args.only == "serving_study":
-            res = serving_study(P, P.LBM_PATTERN_AB if args.path == "ab2" else P.LBM_PATTERN_AA)
+            res = serving_study(P, P.LBM_PATTERN_AA if args.path == "aa" else P.LBM_PATTERN_AB)
         elif args.only == "serving_two_step":
             from paper_1909_13086_amd import serve
             res = serve.bench_serving(P, pattern=P.LBM_PATTERN_AB)

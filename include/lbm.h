@@ -239,16 +239,17 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * reading its lattice once and writing the other once.  Each wavefront walks
  * a strip of 62 (two steps) or 60 (three steps) columns along a segment of
  * segment_rows rows, 1 to 64, keeping three-row windows of the intermediate
- * steps in registers; rows always pass through LDS in three-step launches.
+ * steps in registers (FP64 three-step launches keep the second window in
+ * LDS and load rows directly; the LBM_LAUNCH_STAGED flag applies to
+ * two-step launches).
  * Segment rows are stored per depth (2 and 3); segment_rows = 0 keeps the
  * stored value.  lbm_get_fusion returns the segment rows of the current
  * depth.  Launches never fuse steps across a report step, and step counts
  * that are not a multiple end with a shorter launch.  Batched launches
  * (lbm_step_many) fuse at most two steps, with the two-step segment rows.
- * Results equal those of single steps bit for bit.  Default: FP64 2 steps
- * per launch, segments of 2 rows (its three-step kernel exceeds the register
- * file and spills); FP32 3 steps per launch, segments of 6 rows (two-step
- * segments of 4 rows).  LBM_EINVAL for steps_per_launch outside 1..3 or
+ * Results equal those of single steps bit for bit.  Default: 3 steps per launch
+ * in segments of 4 rows (FP64) or 6 rows (FP32); two-step segments of 2 rows
+ * (FP64) or 4 rows (FP32).  LBM_EINVAL for steps_per_launch outside 1..3 or
  * segment_rows outside 0..64. */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);

@@ -61,14 +61,14 @@ struct LaunchCfg {
 constexpr int kMaxSegmentRows = 64;
 
 // Defaults per precision, the fastest measured on MI355X at 2048x1024 and
-// 4096x2048: FP64 two steps per launch in segments of 2 rows (its three-step
-// kernel does not fit the register file), FP32 three steps per launch in
-// segments of 6 rows (two-step launches, as in the batched path, 4 rows).
+// 4096x2048: three steps per launch in segments of 4 rows (FP64) or 6 rows
+// (FP32); two-step launches (the batched path, shorter remainders) in
+// segments of 2 rows (FP64) or 4 rows (FP32).
 inline LaunchCfg default_launch(int precision) {
   LaunchCfg L;
-  L.fuse = precision == 0 ? 2 : 3;
+  L.fuse = 3;
   L.seg = precision == 0 ? 2 : 4;
-  L.seg3 = 6;
+  L.seg3 = precision == 0 ? 4 : 6;
   return L;
 }
 
@@ -94,7 +94,8 @@ hipError_t launch_step(const CavDev &c, int precision, const LaunchCfg &cfg, hip
 // Two steps of the two-lattice pattern in one launch: reads pop[parity],
 // writes pop[parity ^ 1].
 hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
-// Three steps per launch (two-lattice pattern), rows always staged through LDS.
+// Three steps per launch (two-lattice pattern): FP32 stages rows through LDS,
+// FP64 keeps its level-2 window there and loads rows directly.
 hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
 // entries (the kernel ignores a header that points outside them).

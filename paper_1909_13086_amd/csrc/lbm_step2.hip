@@ -1,4 +1,6 @@
-// Two time steps per launch for the two-lattice pattern (temporal blocking).
+// Two or three time steps per launch for the two-lattice pattern (temporal
+// blocking).  The two-step kernel is described here; the three-step kernel,
+// which extends it by one level, further below.
 //
 // One launch reads the natural state at time t from lattice A once and writes
 // the natural state at t+2 to lattice B once, so a pair of steps moves the
@@ -482,10 +484,12 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 //
 // The same scheme one level deeper: a wavefront owns 60 columns (lanes
 // 2 .. 61) of `seg` rows and walks them with two windows.  Rows are loaded
-// (staged through LDS as above) and collided once (level 1) for the rows
-// y0-2 .. y1+1; the level-1 window feeds the second step (level 2) of rows
-// y0-1 .. y1, whose window feeds the third step (level 3) of the owned rows,
-// which is stored.  Level 2 runs on every lane; only lanes 1 .. 62 hold
+// and collided once (level 1) for the rows y0-2 .. y1+1; the level-1 window
+// feeds the second step (level 2) of rows y0-1 .. y1, whose window feeds the
+// third step (level 3) of the owned rows, which is stored.  FP32 keeps both
+// windows in registers and stages rows through LDS as above (walk3_staged);
+// FP64, whose two windows would exceed the register file, keeps the level-2
+// window in LDS and loads rows directly (walk3_ring).  Level 2 runs on every lane; only lanes 1 .. 62 hold
 // correct values there, which is all level 3 of the owned lanes reads.  Rows
 // outside the cavity give values that no owned cell uses (their links are
 // reflected at the wall).  Each level is the single-step update, so a launch
@@ -562,11 +566,95 @@ __device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, 
   }
 }
 
+// The same three-step walk with the level-2 window kept in LDS instead of
+// registers, for FP64, whose two register windows exceed the register file.
+// Rows are loaded directly (the LDS holds the window, not staged rows).  The
+// window is a ring of two level-2 rows per wavefront, row r in slot r & 1:
+// iteration y reads the populations of row y-D that move along the walk from
+// slot y-D, then overwrites that slot with row y+D; row y is read from its
+// slot when the third step gathers.  Each lane reads and writes only its own
+// column of a slot, and LDS operations of a wavefront complete in order, so
+// no barrier is needed.
+template <typename S, typename R, int D, bool WALLS, int MODEL>
+__device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+                                           S *__restrict__ B, const Col &q, int y0, int y1, R *ring) {
+  const int lane = threadIdx.x & (kWave - 1);
+  auto slot = [&](int r) { return ring + (r & 1) * (kPlanes * kWave) + lane; };
+  auto put = [&](int r, const R (&f)[kQ], const R (&g)[kQ]) {
+    R *p = slot(r);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      p[i * kWave] = f[i];
+      p[(kQ + i) * kWave] = g[i];
+    }
+  };
+  auto get = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
+    const R *p = slot(r);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      f[i] = p[i * kWave];
+      g[i] = p[(kQ + i) * kWave];
+    }
+  };
+  auto get_along = [&](int r, R (&af)[3], R (&ag)[3]) {
+    constexpr int a0 = D > 0 ? 2 : 4, a1 = D > 0 ? 5 : 7, a2 = D > 0 ? 6 : 8;
+    const R *p = slot(r);
+    af[0] = p[a0 * kWave]; af[1] = p[a1 * kWave]; af[2] = p[a2 * kWave];
+    ag[0] = p[(kQ + a0) * kWave]; ag[1] = p[(kQ + a1) * kWave]; ag[2] = p[(kQ + a2) * kWave];
+  };
+  auto level1 = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
+    if (!(row_real<2>(c, r) && q.real)) {
+      zero_row(f, g);
+      return;
+    }
+    load_natural<S, R>(A, c.plane, cell_base(c, q.xw, row_wrap<2>(c, r)), f, g);
+    first_collide<R, MODEL>(c, k, q, r, f, g);
+  };
+  auto level2 = [&](int r, const R (&cf)[kQ], const R (&cg)[kQ], const R (&nf)[kQ],
+                    const R (&ng)[kQ], const R (&af)[3], const R (&ag)[3], R (&f)[kQ], R (&g)[kQ]) {
+    second_collide<R, D, WALLS, MODEL>(c, k, q, r, cf, cg, nf, ng, af, ag, f, g);
+    if (r == 0 && q.strip_flux) add_strip_flux<R>(c, k, q.x, g);
+  };
+
+  const int ys = D > 0 ? y0 : y1 - 1;
+  const int ye = D > 0 ? y1 : y0 - 1;
+  R c1f[kQ], c1g[kQ], n1f[kQ], n1g[kQ], a1f[3], a1g[3];  // level-1 window
+  {
+    R t2f[kQ], t2g[kQ];
+    level1(ys - 2 * D, c1f, c1g);
+    level1(ys - D, n1f, n1g);
+    slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+    level1(ys, n1f, n1g);
+    level2(ys - D, c1f, c1g, n1f, n1g, a1f, a1g, t2f, t2g);
+    put(ys - D, t2f, t2g);
+    slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+    level1(ys + D, n1f, n1g);
+    level2(ys, c1f, c1g, n1f, n1g, a1f, a1g, t2f, t2g);
+    put(ys, t2f, t2g);
+    slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  }
+  for (int y = ys; y != ye; y += D) {
+    R n2f[kQ], n2g[kQ];
+    level1(y + 2 * D, n1f, n1g);
+    level2(y + D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+    slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+    R a2f[3], a2g[3];
+    get_along(y - D, a2f, a2g);
+    put(y + D, n2f, n2g);  // the slot of row y-D
+    R c2f[kQ], c2g[kQ], pf[kQ], pg[kQ];
+    get(y, c2f, c2g);
+    second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
+    emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+  }
+}
+
 template <typename S, typename R, int MODEL>
 __global__ __launch_bounds__(kStagedWaves * kWave)
 __attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int nseg, int seg_rows,
                                                      int order) {
-  __shared__ S lds[kStagedWaves * 2 * kPlanes * kWave];
+  // FP64: level-2 ring of two rows of R; FP32: two staged rows of S
+  constexpr bool kRing = sizeof(R) == 8;
+  __shared__ R lds[kStagedWaves * 2 * kPlanes * kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
@@ -581,18 +669,33 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int
   const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
   S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
   const bool down = (order & 4) && (seg & 1);
-  S *bufs = lds + wid * 2 * kPlanes * kWave;
+  R *mine = lds + wid * 2 * kPlanes * kWave;
   const bool inner = interior_segment<2>(c, x0, y0, y1);
-  if (down) {
-    if (inner)
-      walk3_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
-    else
-      walk3_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+  if constexpr (kRing) {
+    if (down) {
+      if (inner)
+        walk3_ring<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, mine);
+      else
+        walk3_ring<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, mine);
+    } else {
+      if (inner)
+        walk3_ring<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, mine);
+      else
+        walk3_ring<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, mine);
+    }
   } else {
-    if (inner)
-      walk3_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
-    else
-      walk3_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+    S *bufs = reinterpret_cast<S *>(mine);
+    if (down) {
+      if (inner)
+        walk3_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+      else
+        walk3_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+    } else {
+      if (inner)
+        walk3_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+      else
+        walk3_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
+    }
   }
 }
 

@@ -298,17 +298,27 @@ def test_two_step_kernel_in_graphs_and_with_reports(P, chunk):
         assert all(x["total_H"] == y["total_H"] for x, y in zip(sa, sb))
 
 
-def test_two_step_kernel_full_size_matches_oracle(P):
+def test_fused_kernels_full_size_match_oracle(P):
+    """The benchmark's FP64 workload in its launch configuration (three steps
+    per launch, 4-row segments) and with two steps per launch, 6 steps from a
+    random state, against the oracle."""
     case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB)
-    print("case 2048x1024 FP64 two-step kernel, 6 steps vs oracle", flush=True)
+    print("case 2048x1024 FP64 fused kernels, 6 steps vs oracle", flush=True)
     f0, g0 = _random_state(23, 2048, 1024)
-    with P.Context(device=0, max_slots=1) as ctx:  # default launch configuration
-        assert ctx.get_fusion(0) == (2, 2)
-        assert ctx.get_launch(0)[3] == P.LBM_LAUNCH_DEFAULT
-        s = ctx.add(case)
-        ctx.state_load(s, f0, g0)
-        ctx.step(s, 6)
-        got = ctx.fields(s)
+    got = []
+    for fuse in (3, 2):
+        with P.Context(device=0, max_slots=1) as ctx:  # default launch configuration
+            if fuse == 3:
+                assert ctx.get_fusion(0) == (3, 4)
+                assert ctx.get_launch(0)[3] == P.LBM_LAUNCH_DEFAULT
+            else:
+                ctx.set_fusion(0, 2)
+                assert ctx.get_fusion(0) == (2, 2)
+            s = ctx.add(case)
+            ctx.state_load(s, f0, g0)
+            ctx.step(s, 6)
+            got.append(ctx.fields(s))
     o = oracle_run(case, 6, f0, g0)
-    err = max_field_err(got, o.fields())
-    assert max(err.values()) <= 1e-12, err
+    for fields in got:
+        err = max_field_err(fields, o.fields())
+        assert max(err.values()) <= 1e-12, err

@@ -72,8 +72,9 @@ def test_melting_cavity_matches_oracle(P, model, precision):
 
 @pytest.mark.parametrize("model", MODELS)
 def test_two_step_and_batched_paths_equal_single_steps(P, model):
-    """Two-lattice two-step launches (staged and direct) and batched launches
-    of mixed solid models give the single-step results bit for bit."""
+    """Two-lattice launches of two and three steps (rows staged and direct)
+    and batched launches of mixed solid models give the single-step results
+    bit for bit."""
     cases = [dict(_geom_case(130, 40, 0, 0, model), pattern=P.LBM_PATTERN_AB),
              dict(_geom_case(96, 33, 1, 0, 0), pattern=P.LBM_PATTERN_AB),
              dict(_geom_case(77, 21, 0, 0, model), precision=P.LBM_FP32_SHIFTED),
@@ -99,9 +100,20 @@ def test_two_step_and_batched_paths_equal_single_steps(P, model):
                 s = ctx.add(c)
                 ctx.state_load(s, f0, g0)
                 slots.append(s)
-            ctx.step(slots[0], 11)            # single-cavity two-step path
+            ctx.step(slots[0], 11)            # single-cavity fused path (default depth)
             ctx.step_many(slots[1:], [11, 11, 11])  # batched paths
             got = [ctx.state_save(s) for s in slots]
         for k in range(len(cases)):
             assert np.array_equal(got[k][0], want[k][0]) and np.array_equal(got[k][1], want[k][1]), (flags, k)
+    # both fused depths on the single-cavity path, FP64 and FP32
+    for fuse in (2, 3):
+        with P.Context(device=0, max_slots=2) as ctx:
+            for prec in (0, 1):
+                ctx.set_fusion(prec, fuse)
+            for k in (0, 3):
+                s = ctx.add(cases[k])
+                ctx.state_load(s, *states[k])
+                ctx.step(s, 11)
+                f, g = ctx.state_save(s)
+                assert np.array_equal(f, want[k][0]) and np.array_equal(g, want[k][1]), (fuse, k)
 
