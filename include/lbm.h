@@ -249,7 +249,11 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * (lbm_step_many) fuse at most two steps, with the two-step segment rows.
  * Results equal those of single steps bit for bit.  Default: 3 steps per launch
  * in segments of 4 rows (FP64) or 6 rows (FP32); two-step segments of 2 rows
- * (FP64) or 4 rows (FP32).  LBM_EINVAL for steps_per_launch outside 1..3 or
+ * (FP64) or 4 rows (FP32).  Until lbm_set_fusion or lbm_autotune sets it,
+ * the default follows each cavity's size: FP64 cavities below 2^20 cells take
+ * two steps per launch, and three-step segments shrink to 4, 2 or 1 rows
+ * until a launch has at least 1024 wavefronts (lbm_slot_fusion shows the
+ * result); lbm_get_fusion returns the nominal values.  LBM_EINVAL for steps_per_launch outside 1..3 or
  * segment_rows outside 0..64. */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);
@@ -272,6 +276,10 @@ int lbm_sync(lbm_ctx *c);
 int lbm_stream(lbm_ctx *c, void **stream);
 /* Step counter, parity and footprint of a slot. */
 int lbm_slot_info(lbm_ctx *c, int slot, int64_t *step, int32_t *parity, size_t *bytes);
+/* Steps per launch and segment rows that lbm_step uses for this slot (1 for
+ * in-place slots), after the default fusion has followed the cavity size
+ * (lbm_set_fusion).  LBM_EINVAL for a bad slot or NULL outputs. */
+int lbm_slot_fusion(lbm_ctx *c, int slot, int *steps_per_launch, int *segment_rows);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,7 @@ EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_set_case", "lbm_release", "lbm_step", "lbm_reduce",
     "lbm_fields", "lbm_set_report", "lbm_series", "lbm_state_load", "lbm_state_save",
     "lbm_set_launch", "lbm_get_launch", "lbm_set_graph_chunk", "lbm_autotune", "lbm_sync",
-    "lbm_stream", "lbm_slot_info", "lbm_step_many", "lbm_set_group_bytes",
+    "lbm_stream", "lbm_slot_info", "lbm_slot_fusion", "lbm_step_many", "lbm_set_group_bytes",
     "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_set_fusion", "lbm_get_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
     "lbm_server_request", "lbm_server_summary", "lbm_server_on_finish",
@@ -160,6 +160,8 @@ def lib():
             "lbm_stream": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
             "lbm_slot_info": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)]),
+            "lbm_slot_fusion": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_int)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -340,6 +342,12 @@ def lbm_stream(ctx):
     s = ctypes.c_void_p()
     _check(lib().lbm_stream(ctx, ctypes.byref(s)))
     return s.value
+
+
+def lbm_slot_fusion(ctx, slot):
+    n, seg = ctypes.c_int(), ctypes.c_int()
+    _check(lib().lbm_slot_fusion(ctx, int(slot), ctypes.byref(n), ctypes.byref(seg)))
+    return n.value, seg.value
 
 
 def lbm_slot_info(ctx, slot):

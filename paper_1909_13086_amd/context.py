@@ -121,3 +121,6 @@ class Context:
 
     def info(self, slot):
         return L.lbm_slot_info(self.h, slot)
+
+    def slot_fusion(self, slot):
+        return L.lbm_slot_fusion(self.h, slot)

@@ -57,8 +57,11 @@ struct LaunchCfg {
   int fuse = 2;     // steps per launch of the two-lattice pattern (1, 2 or 3)
   int seg = 4;      // rows per wavefront segment of the two-step kernel
   int seg3 = 6;     // rows per wavefront segment of the three-step kernel
+  int adapt = 1;    // default fusion: depth and three-step segments follow the cavity size
 };
 constexpr int kMaxSegmentRows = 64;
+constexpr int kStripCols = kWave - 2;   // owned columns of a two-step wavefront
+constexpr int kStrip3Cols = kWave - 4;  // owned columns of a three-step wavefront
 
 // Defaults per precision, the fastest measured on MI355X at 2048x1024 and
 // 4096x2048: three steps per launch in segments of 4 rows (FP64) or 6 rows

@@ -412,10 +412,31 @@ int enqueue_one_step(lbm_ctx *c, Slot &s) {
   return LBM_OK;
 }
 
+// Launch configuration of a slot.  While the fusion is the default (not set
+// by lbm_set_fusion or lbm_autotune) it follows the cavity size, as measured
+// on MI355X: FP64 cavities below 2^20 cells take two steps per launch (the
+// three-step kernel wins only on larger ones), and three-step segments
+// shrink (6, 4, 2, 1 rows) until the launch has at least 1024 wavefronts,
+// so small cavities still fill the GPU.
+LaunchCfg slot_launch(const lbm_ctx *c, const Slot &s) {
+  LaunchCfg L = c->launch[s.cs.precision];
+  if (!L.adapt || s.cs.pattern != LBM_PATTERN_AB) return L;
+  if (L.fuse == 3 && s.cs.precision == LBM_FP64 && (int64_t)s.cs.nx * s.cs.ny < (int64_t)1 << 20) L.fuse = 2;
+  if (L.fuse == 3) {
+    const int64_t strips = (s.cs.nx + lbm::kStrip3Cols - 1) / lbm::kStrip3Cols;
+    for (int seg : {6, 4, 2, 1}) {
+      if (seg > L.seg3) continue;
+      L.seg3 = seg;
+      if (strips * ((s.cs.ny + seg - 1) / seg) >= 1024) break;
+    }
+  }
+  return L;
+}
+
 // Steps per launch of a slot: two-lattice slots may advance two or three
 // steps per launch, in-place slots one.
 int steps_per_launch(const lbm_ctx *c, const Slot &s) {
-  return s.cs.pattern == LBM_PATTERN_AB ? c->launch[s.cs.precision].fuse : 1;
+  return s.cs.pattern == LBM_PATTERN_AB ? slot_launch(c, s).fuse : 1;
 }
 
 // Slots that the batched launch advances two steps per launch (the batched
@@ -426,7 +447,7 @@ bool fused(const lbm_ctx *c, const Slot &s) { return steps_per_launch(c, s) >= 2
 // steps per launch).  Every launch moves the state to the other lattice of a
 // two-lattice slot; in place it flips the A-A parity.
 hipError_t launch_steps(const lbm_ctx *c, const Slot &s, const CavDev &d, int m) {
-  const LaunchCfg &L = c->launch[s.cs.precision];
+  const LaunchCfg L = slot_launch(c, s);
   if (m == 3) return lbm::launch_step3(d, s.cs.precision, L, c->stream);
   if (m == 2) return lbm::launch_step2(d, s.cs.precision, L, c->stream);
   return lbm::launch_step(d, s.cs.precision, L, c->stream);
@@ -439,14 +460,22 @@ int enqueue_steps(lbm_ctx *c, Slot &s, int m) {
   return LBM_OK;
 }
 
-// Launches of a chunk of n steps starting from parity p: launches of the
-// slot's steps per launch, then one shorter launch for the rest.  Returns the
-// storage parity after the chunk.
+// Steps of the next launch when `left` steps remain before the next stop
+// (a report or the end of the request): the slot's steps per launch, fewer
+// at the end, and two instead of three when four remain (two two-step
+// launches cost less than a three-step and a single step).
+int64_t next_launch_steps(int F, int64_t left) {
+  if (F == 3 && left == 4) return 2;
+  return std::min<int64_t>(F, left);
+}
+
+// Launches of a chunk of n steps starting from parity p (next_launch_steps).
+// Returns the storage parity after the chunk.
 int enqueue_chunk(lbm_ctx *c, const Slot &s, CavDev d, int n, hipError_t *err) {
   const int F = steps_per_launch(c, s);
   *err = hipSuccess;
   for (int k = 0; k < n && *err == hipSuccess;) {
-    const int m = std::min(F, n - k);
+    const int m = (int)next_launch_steps(F, n - k);
     *err = launch_steps(c, s, d, m);
     d.parity ^= 1;
     k += m;
@@ -512,7 +541,7 @@ int step_slot(lbm_ctx *c, Slot &s, int64_t n) {
       n -= chunk;
     } else {
       // as many fused steps as fit before the next report
-      const int64_t m = std::min<int64_t>({(int64_t)steps_per_launch(c, s), n, next - s.step});
+      const int64_t m = next_launch_steps(steps_per_launch(c, s), std::min<int64_t>(n, next - s.step));
       rc = m >= 2 ? enqueue_steps(c, s, (int)m) : enqueue_one_step(c, s);
       n -= m >= 2 ? m : 1;
     }
@@ -532,7 +561,7 @@ namespace {
 
 constexpr int kBatchTileX = 64;
 constexpr int kBatchTileRows = 16;
-constexpr int kStrip2Cols = lbm::kWave - 2;  // owned columns of a two-step wavefront
+constexpr int kStrip2Cols = lbm::kStripCols;
 
 // Launches of a cache group come per precision, kind (one-step tiles or
 // two-step segments) and solid model; each has a {first, count} header.
@@ -1129,6 +1158,7 @@ int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_
     return fail(LBM_EINVAL, "steps per launch in {1, 2, 3}, segment rows in 0..64");
   LaunchCfg &L = c->launch[precision];
   L.fuse = steps_per_launch;
+  L.adapt = 0;
   if (segment_rows > 0) (steps_per_launch == 3 ? L.seg3 : L.seg) = segment_rows;
   for (auto &s : c->slots) drop_graphs(s);
   c->batch.dirty = true;  // item lists depend on the fusion
@@ -1164,6 +1194,17 @@ int lbm_sync(lbm_ctx *c) {
 int lbm_stream(lbm_ctx *c, void **stream) {
   if (!c || !stream) return fail(LBM_EINVAL, "NULL argument");
   *stream = c->stream;
+  return LBM_OK;
+}
+
+int lbm_slot_fusion(lbm_ctx *c, int slot, int *steps, int *rows) {
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  if (!steps || !rows) return fail(LBM_EINVAL, "NULL argument");
+  const Slot &s = c->slots[slot];
+  const LaunchCfg L = slot_launch(c, s);
+  *steps = steps_per_launch(c, s);
+  *rows = *steps == 3 ? L.seg3 : L.seg;
   return LBM_OK;
 }
 

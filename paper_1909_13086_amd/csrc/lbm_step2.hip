@@ -33,8 +33,6 @@ namespace {
 
 using namespace dev;
 
-constexpr int kStripCols = kWave - 2;  // owned columns per wavefront (two steps)
-constexpr int kStrip3Cols = kWave - 4; // owned columns per wavefront (three steps)
 constexpr int kDirectWaves = 4;        // wavefronts per workgroup, direct rows
 constexpr int kStagedWaves = 2;        // wavefronts per workgroup, staged rows
 

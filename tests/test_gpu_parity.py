@@ -322,3 +322,38 @@ def test_fused_kernels_full_size_match_oracle(P):
     for fields in got:
         err = max_field_err(fields, o.fields())
         assert max(err.values()) <= 1e-12, err
+
+
+def test_default_fusion_follows_cavity_size(P):
+    """The default fusion adapts to the cavity (FP64 below 2^20 cells: two
+    steps per launch; three-step segments shrink until a launch has at least
+    1024 wavefronts); an explicit setting is used as given.  The adapted
+    launches equal single steps bit for bit."""
+    print("case default fusion per cavity size", flush=True)
+    cases = [((2048, 1024, 0), (3, 4)), ((1024, 512, 0), (2, 2)), ((2048, 1024, 1), (3, 6)),
+             ((1024, 512, 1), (3, 6)), ((768, 384, 1), (3, 4)), ((512, 256, 1), (3, 2)),
+             ((128, 64, 1), (3, 1))]
+    with P.Context(device=0, max_slots=len(cases) + 1) as ctx:
+        for (nx, ny, prec), want in cases:
+            s = ctx.add(dict(cavity(nx, ny), precision=prec, pattern=P.LBM_PATTERN_AB))
+            assert ctx.slot_fusion(s) == want, (nx, ny, prec)
+            ctx.release(s)
+        s = ctx.add(dict(cavity(128, 64), pattern=P.LBM_PATTERN_AA))
+        assert ctx.slot_fusion(s)[0] == 1
+        ctx.release(s)
+        ctx.set_fusion(0, 3, 6)
+        s = ctx.add(dict(cavity(256, 128), pattern=P.LBM_PATTERN_AB))
+        assert ctx.slot_fusion(s) == (3, 6) and ctx.get_fusion(0) == (3, 6)
+    # adapted three-step launches of a small FP32 cavity (1-row segments)
+    case = dict(cavity(128, 64, heater_center=0.4), precision=P.LBM_FP32_SHIFTED, pattern=P.LBM_PATTERN_AB)
+    f0, g0 = _random_state(57, 128, 64)
+    out = []
+    for fuse in (None, 1):
+        with P.Context(device=0, max_slots=1) as ctx:
+            if fuse:
+                ctx.set_fusion(1, fuse)
+            s = ctx.add(case)
+            ctx.state_load(s, f0, g0)
+            ctx.step(s, 14)
+            out.append(ctx.state_save(s))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
