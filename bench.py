@@ -226,8 +226,8 @@ def fused_sizes_variant(P, steps=480):
 def batched_variant(P, steps, chunk=100, pattern=None):
     """64 cavities of uneven size (seeded sweep), FP32 shifted: batched
     launches replayed from captured 100-step graphs (in place: one launch per
-    step; two lattices: one launch per two steps), against the same cavities
-    solved one after another with the single-cavity path."""
+    step; two lattices: one launch per three steps, the FP32 default), against
+    the same cavities solved one after another with the single-cavity path."""
     import torch
     from btrirt_workloads import batch_sweep
     pattern = P.LBM_PATTERN_AA if pattern is None else pattern
@@ -255,7 +255,7 @@ def batched_variant(P, steps, chunk=100, pattern=None):
     ctx.close()
     lu = cells * steps
     res = dict(cavities=len(cases), cells=cells, steps=steps,
-               pattern="in place" if pattern == P.LBM_PATTERN_AA else "two lattices, two steps per launch",
+               pattern="in place" if pattern == P.LBM_PATTERN_AA else "two lattices, three steps per launch",
                batched_mlups=round(lu / (ms_b * 1e-3) / 1e6, 1),
                sequential_mlups=round(lu / (ms_s * 1e-3) / 1e6, 1))
     res["speedup"] = round(res["batched_mlups"] / res["sequential_mlups"], 3)

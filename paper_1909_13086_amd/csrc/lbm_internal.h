@@ -114,7 +114,14 @@ hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
 hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
                               const int32_t *hdr_dev, int item_cap, int precision, int model,
                               const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s);
-// Workgroups of a batched two-step launch that fill the device once.
+// Batched three-step launch over 60-column strip segments (cfg.seg3 rows):
+// launch j advances cavity c by three steps while 3 j + 3 <= active_steps(c),
+// by the one or two steps left when 3 j < active_steps(c) < 3 j + 3, else
+// leaves it.
+hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
+                              const int32_t *hdr_dev, int item_cap, int precision, int model,
+                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s);
+// Workgroups of a batched two- or three-step launch that fill the device once.
 int step2_batch_grid(int num_cus);
 hipError_t launch_reduce(const CavDev &c, int precision, double *partials, StatsDev *out,
                          hipStream_t s);

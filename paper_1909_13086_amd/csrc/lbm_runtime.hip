@@ -251,11 +251,13 @@ struct Batch {
   std::vector<int> members;       // slot ids in cavity-array order
   std::vector<int> group_precs;   // per group: bit launch_bit(p, kind, model) set when it holds
                                   // such launches (kind 0: one step per launch over tiles,
-                                  // kind 1: two-step launches over strip segments)
+                                  // kind 1 / 2: two- / three-step launches over strip segments)
+  std::vector<int> hdr_seg;       // per header: segment rows of its fused launches
   bool dirty = true;
   hipGraphExec_t graph = nullptr; // valid while the device buffers and the group shape stay
   int graph_chunk = 0;
   std::vector<int> graph_shape;   // group_precs the graph was captured for
+  std::vector<int> graph_segs;    // hdr_seg the graph was captured for
 };
 
 }  // namespace
@@ -439,10 +441,6 @@ int steps_per_launch(const lbm_ctx *c, const Slot &s) {
   return s.cs.pattern == LBM_PATTERN_AB ? slot_launch(c, s).fuse : 1;
 }
 
-// Slots that the batched launch advances two steps per launch (the batched
-// kernel fuses at most two).
-bool fused(const lbm_ctx *c, const Slot &s) { return steps_per_launch(c, s) >= 2; }
-
 // One launch advancing the state by m steps (1, 2 or 3, at most the slot's
 // steps per launch).  Every launch moves the state to the other lattice of a
 // two-lattice slot; in place it flips the A-A parity.
@@ -563,10 +561,12 @@ constexpr int kBatchTileX = 64;
 constexpr int kBatchTileRows = 16;
 constexpr int kStrip2Cols = lbm::kStripCols;
 
-// Launches of a cache group come per precision, kind (one-step tiles or
-// two-step segments) and solid model; each has a {first, count} header.
-constexpr int kLaunchKinds = 2 * 2 * 3;
-int launch_bit(int prec, int kind, int model) { return (prec * 2 + kind) * 3 + model; }
+// Launches of a cache group come per precision, kind (one-step tiles, two-
+// or three-step segments) and solid model; each has a {first, count} header.
+constexpr int kLaunchKinds = 2 * 3 * 3;
+int launch_bit(int prec, int kind, int model) { return (prec * 3 + kind) * 3 + model; }
+// kind of a slot's batched launches: its steps per launch - 1
+int batch_kind(const lbm_ctx *c, const Slot &s) { return steps_per_launch(c, s) - 1; }
 int hdr_index(int g, int prec, int kind, int model) {
   return (g * kLaunchKinds + launch_bit(prec, kind, model)) * 2;
 }
@@ -612,18 +612,58 @@ int rebuild_batch(lbm_ctx *c) {
     group_of[j] = ngroups - 1;
   }
   const size_t ncav = b.members.size();
-  // work items: 64 x 16 tiles for one-step cavities, strip segments
-  // (62 columns x seg rows, one wavefront each) for two-step cavities
-  auto items_of = [&](const Slot &s) -> size_t {
-    if (fused(c, s)) {
-      const int seg = c->launch[s.cs.precision].seg;
-      return (size_t)((s.cs.nx + kStrip2Cols - 1) / kStrip2Cols) * ((s.cs.ny + seg - 1) / seg);
-    }
-    return (size_t)((s.cs.nx + kBatchTileX - 1) / kBatchTileX) *
-           ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
+  auto cols_of = [](int kind) { return kind == 2 ? lbm::kStrip3Cols : kStrip2Cols; };
+  auto segs_of = [](const Slot &s, int cols, int seg) -> int64_t {
+    return (int64_t)((s.cs.nx + cols - 1) / cols) * ((s.cs.ny + seg - 1) / seg);
   };
+  // Segment rows of each fused launch.  While the fusion is the default they
+  // balance the launch: its wavefronts (one per segment) take segments in
+  // passes of step2_batch_grid x 2, and a segment of seg rows costs about
+  // (kind + 1) seg + kind (kind + 1) collisions per row, so the rows that
+  // minimise passes x cost are taken (a launch of few segments prefers short
+  // ones, one just above a full pass longer ones).
+  const int64_t wave_slots = (int64_t)lbm::step2_batch_grid(c->num_cus) * 2;
+  b.hdr_seg.assign((size_t)std::max(ngroups, 1) * kLaunchKinds, 0);
+  for (int g = 0; g < ngroups; ++g)
+    for (int prec = 0; prec < 2; ++prec)
+      for (int kind = 1; kind < 3; ++kind)
+        for (int model = 0; model < 3; ++model) {
+          const LaunchCfg &L = c->launch[prec];
+          int best = kind == 2 ? L.seg3 : L.seg;
+          if (L.adapt) {
+            double best_cost = 1e300;
+            for (int seg = 1; seg <= 16; ++seg) {
+              int64_t items = 0;
+              for (size_t j = 0; j < ncav; ++j) {
+                const Slot &s = c->slots[b.members[j]];
+                if (group_of[j] == g && s.cs.precision == prec && batch_kind(c, s) == kind &&
+                    s.cs.solid_model == model)
+                  items += segs_of(s, cols_of(kind), seg);
+              }
+              if (items == 0) break;
+              const double cost =
+                  (double)((items + wave_slots - 1) / wave_slots) * ((kind + 1) * seg + kind * (kind + 1));
+              if (cost < best_cost) {
+                best_cost = cost;
+                best = seg;
+              }
+            }
+          }
+          b.hdr_seg[hdr_index(g, prec, kind, model) / 2] = best;
+        }
+  // work items: 64 x 16 tiles for one-step cavities, strip segments (62
+  // columns for two steps, 60 for three, one wavefront each) for fused ones
   size_t ntiles = 0;
-  for (int id : b.members) ntiles += items_of(c->slots[id]);
+  for (size_t j = 0; j < ncav; ++j) {
+    const Slot &s = c->slots[b.members[j]];
+    const int kind = batch_kind(c, s);
+    if (kind == 0)
+      ntiles += (size_t)((s.cs.nx + kBatchTileX - 1) / kBatchTileX) *
+                ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
+    else
+      ntiles += (size_t)segs_of(s, cols_of(kind),
+                                b.hdr_seg[hdr_index(group_of[j], s.cs.precision, kind, s.cs.solid_model) / 2]);
+  }
   const size_t nhdr = (size_t)std::max(ngroups, 1) * kLaunchKinds * 2;
   HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
   if (ncav > b.cav_cap || ntiles > b.tile_cap || nhdr > b.hdr_cap) {
@@ -643,22 +683,23 @@ int rebuild_batch(lbm_ctx *c) {
   size_t t = 0;
   for (int g = 0; g < ngroups; ++g) {
     for (int prec = 0; prec < 2; ++prec) {
-      for (int kind = 0; kind < 2; ++kind) {
+      for (int kind = 0; kind < 3; ++kind) {
         for (int model = 0; model < 3; ++model) {
           const size_t first = t;
           for (size_t j = 0; j < ncav; ++j) {
             if (group_of[j] != g) continue;
             const Slot &s = c->slots[b.members[j]];
-            if (s.cs.precision != prec || (int)fused(c, s) != kind || s.cs.solid_model != model)
+            if (s.cs.precision != prec || batch_kind(c, s) != kind || s.cs.solid_model != model)
               continue;
             if (kind == 0) {
               for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
                 for (int x0 = 0; x0 < s.cs.nx; x0 += kBatchTileX)
                   b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, 0};
             } else {
-              const int seg = c->launch[prec].seg;
+              const int seg = b.hdr_seg[hdr_index(g, prec, kind, model) / 2];
+              const int cols = cols_of(kind);
               for (int y0 = 0, k = 0; y0 < s.cs.ny; y0 += seg, ++k)
-                for (int x0 = 0; x0 < s.cs.nx; x0 += kStrip2Cols)
+                for (int x0 = 0; x0 < s.cs.nx; x0 += cols)
                   b.tiles_host[t++] = BatchTile{(int32_t)j, x0, y0, k};
             }
           }
@@ -683,8 +724,9 @@ int rebuild_batch(lbm_ctx *c) {
 
 int batch_grid(lbm_ctx *c) { return c->num_cus * 8; }
 
-// Launches of one chunk: per cache group, `chunk` one-step launches and
-// ceil(chunk / 2) two-step launches for each precision present.
+// Launches of one chunk: per cache group, `chunk` one-step launches,
+// ceil(chunk / 2) two-step and ceil(chunk / 3) three-step launches for each
+// precision present.
 hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
   Batch &b = c->batch;
   hipError_t err = hipSuccess;
@@ -700,11 +742,25 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
     for (int j = 0; j < (chunk + 1) / 2 && err == hipSuccess; ++j)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
         for (int model = 0; model < 3 && err == hipSuccess; ++model)
-          if (b.group_precs[g] & (1 << launch_bit(prec, 1, model)))
+          if (b.group_precs[g] & (1 << launch_bit(prec, 1, model))) {
+            LaunchCfg L = c->launch[prec];
+            L.seg = b.hdr_seg[hdr_index(g, prec, 1, model) / 2];
             err = lbm::launch_step2_batch(b.cavs_dev, b.tiles_dev,
                                           b.hdr_dev + hdr_index(g, prec, 1, model),
-                                          (int)b.tile_cap, prec, model, c->launch[prec], j,
+                                          (int)b.tile_cap, prec, model, L, j,
                                           lbm::step2_batch_grid(c->num_cus), c->stream);
+          }
+    for (int j = 0; j < (chunk + 2) / 3 && err == hipSuccess; ++j)
+      for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
+        for (int model = 0; model < 3 && err == hipSuccess; ++model)
+          if (b.group_precs[g] & (1 << launch_bit(prec, 2, model))) {
+            LaunchCfg L = c->launch[prec];
+            L.seg3 = b.hdr_seg[hdr_index(g, prec, 2, model) / 2];
+            err = lbm::launch_step3_batch(b.cavs_dev, b.tiles_dev,
+                                          b.hdr_dev + hdr_index(g, prec, 2, model),
+                                          (int)b.tile_cap, prec, model, L, j,
+                                          lbm::step2_batch_grid(c->num_cus), c->stream);
+          }
   }
   return err;
 }
@@ -750,7 +806,8 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
                            hipMemcpyHostToDevice, c->stream));
     const bool use_graph = c->graph_chunk > 0 && chunk == c->graph_chunk;
     if (use_graph) {
-      if (!b.graph || b.graph_chunk != chunk || b.graph_shape != b.group_precs) {
+      if (!b.graph || b.graph_chunk != chunk || b.graph_shape != b.group_precs ||
+          b.graph_segs != b.hdr_seg) {
         drop_batch_graph(c);
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -768,6 +825,7 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
         }
         b.graph_chunk = chunk;
         b.graph_shape = b.group_precs;
+        b.graph_segs = b.hdr_seg;
       }
       HIP_TRY(hipGraphLaunch(b.graph, c->stream));
     } else {
@@ -778,7 +836,8 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
       const int64_t adv = std::min<int64_t>(left[id], chunk);
       s.step += adv;
       // one parity flip per launch that advanced the slot
-      const int64_t launches = fused(c, s) ? (adv + 1) / 2 : adv;
+      const int F = batch_kind(c, s) + 1;
+      const int64_t launches = (adv + F - 1) / F;
       if (launches & 1) s.dev.parity ^= 1;
       left[id] -= adv;
     }

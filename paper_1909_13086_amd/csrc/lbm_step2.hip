@@ -205,13 +205,14 @@ __device__ __forceinline__ void store_interior(const CavDev &c, S *__restrict__ 
 }
 
 // Stores of an owned cell's second step (and its strip flux).
-template <typename S, typename R, bool WALLS = true>
+// FLUX = false: the strip flux of this step was already counted.
+template <typename S, typename R, bool WALLS = true, bool FLUX = true>
 __device__ __forceinline__ void emit(const CavDev &c, const Coef<R> &k, S *__restrict__ B, const Col &q,
                                      int y, const R (&pf)[kQ], const R (&pg)[kQ]) {
   if (q.owner) {
     if constexpr (WALLS) {
       store_scatter<S, R>(c, k, B, q.x, y, cell_base(c, q.x, y), pf, pg);
-      if (q.bottom_hot && y == 0) add_strip_flux<R>(c, k, q.x, pg);
+      if (FLUX && q.bottom_hot && y == 0) add_strip_flux<R>(c, k, q.x, pg);
     } else {
       store_interior<S, R>(c, B, q.x, y, pf, pg);
     }
@@ -494,8 +495,11 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 // equals three single two-lattice steps bit for bit.
 //
 // Iteration y of the walk (direction D) computes level 1 of row y+2D, level 2
-// of row y+D and level 3 of row y, then slides both windows by one row.
-template <typename S, typename R, int D, bool WALLS, int MODEL>
+// of row y+D and level 3 of row y, then slides both windows by one row.  With
+// STEPS = 2 the walk stores level 2 of the owned rows instead (a batched
+// launch whose cavity has two steps left); its strip flux is counted where
+// level 2 is computed.
+template <typename S, typename R, int D, bool WALLS, int MODEL, int STEPS = 3>
 __device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
                                              S *__restrict__ B, const Col &q, int y0, int y1, int x0,
                                              S *bufs) {
@@ -555,10 +559,15 @@ __device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, 
     if (y + D != ye) issue(y + 3 * D, b ^ 1);
     level1(y + 2 * D, b, n1f, n1g);
     level2(y + D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
-    R pf[kQ], pg[kQ];
-    second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
-    wait_vm();
-    emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+    if constexpr (STEPS == 3) {
+      R pf[kQ], pg[kQ];
+      second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
+      wait_vm();
+      emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+    } else {
+      wait_vm();
+      emit<S, R, WALLS, false>(c, k, B, q, y, c2f, c2g);
+    }
     slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
     slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
   }
@@ -573,7 +582,7 @@ __device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, 
 // slot when the third step gathers.  Each lane reads and writes only its own
 // column of a slot, and LDS operations of a wavefront complete in order, so
 // no barrier is needed.
-template <typename S, typename R, int D, bool WALLS, int MODEL>
+template <typename S, typename R, int D, bool WALLS, int MODEL, int STEPS = 3>
 __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
                                            S *__restrict__ B, const Col &q, int y0, int y1, R *ring) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -636,13 +645,55 @@ __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, co
     level1(y + 2 * D, n1f, n1g);
     level2(y + D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
     slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
-    R a2f[3], a2g[3];
-    get_along(y - D, a2f, a2g);
-    put(y + D, n2f, n2g);  // the slot of row y-D
-    R c2f[kQ], c2g[kQ], pf[kQ], pg[kQ];
-    get(y, c2f, c2g);
-    second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
-    emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+    if constexpr (STEPS == 3) {
+      R a2f[3], a2g[3];
+      get_along(y - D, a2f, a2g);
+      put(y + D, n2f, n2g);  // the slot of row y-D
+      R c2f[kQ], c2g[kQ], pf[kQ], pg[kQ];
+      get(y, c2f, c2g);
+      second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
+      emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+    } else {
+      R c2f[kQ], c2g[kQ];
+      get(y, c2f, c2g);
+      put(y + D, n2f, n2g);
+      emit<S, R, WALLS, false>(c, k, B, q, y, c2f, c2g);
+    }
+  }
+}
+
+// The three-step walk for either precision, direction and wall case.
+template <typename S, typename R, int MODEL, int STEPS>
+__device__ __forceinline__ void walk3(bool down, bool inner, const CavDev &c, const Coef<R> &k,
+                                      const S *__restrict__ A, S *__restrict__ B, const Col &q, int y0,
+                                      int y1, int x0, R *mine) {
+  if constexpr (sizeof(R) == 8) {
+    // FP64: level-2 ring of two rows of R
+    if (down) {
+      if (inner)
+        walk3_ring<S, R, -1, false, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+      else
+        walk3_ring<S, R, -1, true, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+    } else {
+      if (inner)
+        walk3_ring<S, R, +1, false, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+      else
+        walk3_ring<S, R, +1, true, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+    }
+  } else {
+    // FP32: two staged rows of S
+    S *bufs = reinterpret_cast<S *>(mine);
+    if (down) {
+      if (inner)
+        walk3_staged<S, R, -1, false, MODEL, STEPS>(c, k, A, B, q, y0, y1, x0, bufs);
+      else
+        walk3_staged<S, R, -1, true, MODEL, STEPS>(c, k, A, B, q, y0, y1, x0, bufs);
+    } else {
+      if (inner)
+        walk3_staged<S, R, +1, false, MODEL, STEPS>(c, k, A, B, q, y0, y1, x0, bufs);
+      else
+        walk3_staged<S, R, +1, true, MODEL, STEPS>(c, k, A, B, q, y0, y1, x0, bufs);
+    }
   }
 }
 
@@ -650,8 +701,6 @@ template <typename S, typename R, int MODEL>
 __global__ __launch_bounds__(kStagedWaves * kWave)
 __attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int nseg, int seg_rows,
                                                      int order) {
-  // FP64: level-2 ring of two rows of R; FP32: two staged rows of S
-  constexpr bool kRing = sizeof(R) == 8;
   __shared__ R lds[kStagedWaves * 2 * kPlanes * kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -668,33 +717,7 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int
   S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
   const bool down = (order & 4) && (seg & 1);
   R *mine = lds + wid * 2 * kPlanes * kWave;
-  const bool inner = interior_segment<2>(c, x0, y0, y1);
-  if constexpr (kRing) {
-    if (down) {
-      if (inner)
-        walk3_ring<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, mine);
-      else
-        walk3_ring<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, mine);
-    } else {
-      if (inner)
-        walk3_ring<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, mine);
-      else
-        walk3_ring<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, mine);
-    }
-  } else {
-    S *bufs = reinterpret_cast<S *>(mine);
-    if (down) {
-      if (inner)
-        walk3_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
-      else
-        walk3_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
-    } else {
-      if (inner)
-        walk3_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
-      else
-        walk3_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, x0, bufs);
-    }
-  }
+  walk3<S, R, MODEL, 3>(down, interior_segment<2>(c, x0, y0, y1), c, k, A, B, q, y0, y1, x0, mine);
 }
 
 template <typename S, typename R>
@@ -780,6 +803,67 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restr
   }
 }
 
+// Batched three-step launch: items are 60-column strip segments of the
+// three-step cavities, taken as in the two-step batched launch.  Launch j of
+// a chunk advances a cavity by three steps while 3j + 3 <= active_steps, and
+// by the one or two steps left of the chunk otherwise (a walk that stores
+// level 2, or single steps of the segment's owned cells).
+template <typename S, typename R, int MODEL>
+__global__ __launch_bounds__(kStagedWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(2))) void k_step3_batch(const CavDev *__restrict__ cavs,
+                                                           const BatchTile *__restrict__ items,
+                                                           const int32_t *__restrict__ hdr,
+                                                           int item_cap, int seg_rows,
+                                                           int launch_index, int order) {
+  __shared__ R lds[kStagedWaves * 2 * kPlanes * kWave];
+  const int first = hdr[0], n = hdr[1];
+  if (first < 0 || n <= 0 || first > item_cap - n) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
+  const int nbx = (gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int t0 = (int)((int64_t)n * xcd / kXcds);
+  const int t1 = (int)((int64_t)n * (xcd + 1) / kXcds);
+  R *mine = lds + wid * 2 * kPlanes * kWave;
+  for (int t = t0 + lb * kStagedWaves + wid; t < t1; t += nbx * kStagedWaves) {  // uniform per wavefront
+    const BatchTile it = items[first + t];
+    CavDev c = cavs[it.cav];
+    const int left = c.active_steps - 3 * launch_index;
+    if (left <= 0) continue;
+    c.parity ^= (launch_index & 1);
+    const int y0 = it.y0;
+    const int y1 = min(y0 + seg_rows, c.ny);
+    const Coef<R> k(c);
+    const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
+    S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
+    const Col q = make_col<2>(c, it.x0 - 2 + lane, lane, y0);
+    if (left == 1) {
+      if (q.owner)
+        for (int y = y0; y < y1; ++y) update_cell<S, R, MODEL>(c, k, 2, q.x, y);
+      continue;
+    }
+    const bool down = (order & 4) && (it.pad & 1);
+    const bool inner = interior_segment<2>(c, it.x0, y0, y1);
+    if (left >= 3)
+      walk3<S, R, MODEL, 3>(down, inner, c, k, A, B, q, y0, y1, it.x0, mine);
+    else
+      walk3<S, R, MODEL, 2>(down, inner, c, k, A, B, q, y0, y1, it.x0, mine);
+  }
+}
+
+template <typename S, typename R>
+hipError_t dispatch3_batch(const CavDev *cavs, const BatchTile *items, const int32_t *hdr, int item_cap,
+                           int model, const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
+  if (cfg.seg3 < 1 || cfg.seg3 > kMaxSegmentRows) return hipErrorInvalidValue;
+  const int order = cfg.zigzag ? 4 : 0;
+  with_model(model, [&](auto m) {
+    hipLaunchKernelGGL((k_step3_batch<S, R, decltype(m)::value>), dim3(grid), dim3(kStagedWaves * kWave), 0,
+                       s, cavs, items, hdr, item_cap, cfg.seg3, launch_index, order);
+    return 0;
+  });
+  return hipGetLastError();
+}
+
 template <typename S, typename R, bool STAGED>
 hipError_t dispatch_batch(const CavDev *cavs, const BatchTile *items, const int32_t *hdr,
                           int item_cap, int model, const LaunchCfg &cfg, int launch_index,
@@ -817,6 +901,15 @@ hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev
                                                      cfg, launch_index, grid, s)
              : dispatch_batch<float, float, false>(cavs_dev, items_dev, hdr_dev, item_cap, model,
                                                    cfg, launch_index, grid, s);
+}
+
+hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
+                              const int32_t *hdr_dev, int item_cap, int precision, int model,
+                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
+  return precision == 0 ? dispatch3_batch<double, double>(cavs_dev, items_dev, hdr_dev, item_cap, model,
+                                                          cfg, launch_index, grid, s)
+                        : dispatch3_batch<float, float>(cavs_dev, items_dev, hdr_dev, item_cap, model,
+                                                        cfg, launch_index, grid, s);
 }
 
 hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {

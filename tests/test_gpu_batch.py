@@ -101,12 +101,14 @@ def _ab_cases(P):
     ]
 
 
-@pytest.mark.parametrize("flags,seg", [(None, None), (13, 5), (21, 3), (29, 1)])
-def test_two_step_batch_uneven_steps_equal_solo(P, flags, seg):
-    """Two-lattice cavities advance two steps per batched launch (one step for
-    an odd remainder), next to an in-place cavity, with per-slot step counts,
-    graph chunks and every launch mode of the two-step kernel."""
-    print(f"case two-step batch flags={flags} seg={seg}", flush=True)
+@pytest.mark.parametrize("fuse,flags,seg,chunk", [(None, None, None, 4), (2, 13, 5, 4), (2, 21, 3, 4),
+                                                  (2, 29, 1, 4), (3, None, None, 5), (3, 29, 2, 4),
+                                                  (3, 21, 1, 5)])
+def test_fused_batch_uneven_steps_equal_solo(P, fuse, flags, seg, chunk):
+    """Two-lattice cavities advance two or three steps per batched launch (the
+    one or two steps left of a chunk in its last launch), next to an in-place
+    cavity, with per-slot step counts, graph chunks and every launch mode."""
+    print(f"case fused batch fuse={fuse} flags={flags} seg={seg} chunk={chunk}", flush=True)
     cases = _ab_cases(P)
     states = [_random_state(70 + k, c["nx"], c["ny"]) for k, c in enumerate(cases)]
     counts = [7, 12, 1, 9]
@@ -114,9 +116,9 @@ def test_two_step_batch_uneven_steps_equal_solo(P, flags, seg):
         for prec in (0, 1):
             if flags is not None:
                 ctx.set_launch(prec, 256, 1, 1, flags)
-            if seg is not None:
-                ctx.set_fusion(prec, 2, seg)
-        ctx.set_graph_chunk(4)
+            if fuse is not None:
+                ctx.set_fusion(prec, fuse, seg)
+        ctx.set_graph_chunk(chunk)
         slots = []
         for c, (f0, g0) in zip(cases, states):
             s = ctx.add(c)
