@@ -245,16 +245,18 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * Segment rows are stored per depth (2 and 3); segment_rows = 0 keeps the
  * stored value.  lbm_get_fusion returns the segment rows of the current
  * depth.  Launches never fuse steps across a report step, and step counts
- * that are not a multiple end with a shorter launch.  Batched launches
- * (lbm_step_many) fuse at most two steps, with the two-step segment rows.
- * Results equal those of single steps bit for bit.  Default: 3 steps per launch
- * in segments of 4 rows (FP64) or 6 rows (FP32); two-step segments of 2 rows
- * (FP64) or 4 rows (FP32).  Until lbm_set_fusion or lbm_autotune sets it,
- * the default follows each cavity's size: FP64 cavities below 2^20 cells take
- * two steps per launch, and three-step segments shrink to 4, 2 or 1 rows
- * until a launch has at least 1024 wavefronts (lbm_slot_fusion shows the
- * result); lbm_get_fusion returns the nominal values.  LBM_EINVAL for steps_per_launch outside 1..3 or
- * segment_rows outside 0..64. */
+ * that are not a multiple end with shorter launches.  Batched launches
+ * (lbm_step_many) fuse as many steps as the slot's single-cavity launches.
+ * Results equal those of single steps bit for bit.  Default: 3 steps per
+ * launch in segments of 4 rows (FP64) or 6 rows (FP32); two-step segments
+ * of 2 rows (FP64) or 4 rows (FP32).  Until lbm_set_fusion or lbm_autotune
+ * sets it, the default follows each cavity's size: FP64 cavities below 2^20
+ * cells take two steps per launch, three-step segments shrink to 4, 2 or 1
+ * rows until a launch has at least 1024 wavefronts (lbm_slot_fusion shows
+ * the result), and batched launches choose their segment rows per cache
+ * group so that the group's segments fill the device's wavefronts evenly;
+ * lbm_get_fusion returns the nominal values.  LBM_EINVAL for
+ * steps_per_launch outside 1..3 or segment_rows outside 0..64. */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
