@@ -323,7 +323,7 @@ def heater_study(P, fo_end, precision, every_fo=0.005):
     """Heater-position study of Sec. 3.2 (the liquid-fraction curves of Fig. 3b):
     square 512x512 cavity, Ra = 1e8, Pr = 6.2, Ste = 0.125, heater width
     D = 0.5 L at centres C = 0.25, 0.375, 0.5 L, all three advanced together in
-    batched two-step launches on two lattices; melt fraction and Nusselt number
+    fused batched launches on two lattices; melt fraction and Nusselt number
     every `every_fo` in Fourier number up to `fo_end`."""
     from btrirt_workloads import cavity
     cs = [0.25, 0.375, 0.5]
@@ -359,7 +359,7 @@ def solid_study(P, fo_end, precision, every_fo=0.01, n=256):
     Carman-Kozeny drag, partial bounce-back) and the free rate k0 of the
     enthalpy populations (0.6, 1.0, 1.4 with the scaled velocity).  Square
     n x n cavity, Ra = 1e7, Pr = 6.2, Ste = 0.125, heater centred with width
-    0.5 L; all cases advance together in batched two-step launches."""
+    0.5 L; all cases advance together in fused batched launches."""
     from btrirt_workloads import cavity
     base = dict(cavity(n, n, Ra=1e7, Pr=6.2, Ste=0.125, heater_center=0.5, heater_width=0.5),
                 precision=precision, pattern=P.LBM_PATTERN_AB)
