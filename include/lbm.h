@@ -184,7 +184,9 @@ int lbm_step_many(lbm_ctx *c, int count, const int32_t *slots, const int64_t *ns
 /* Capacity of one cache group of the batched launch (default 160 MiB): within
  * a chunk of graph-replayed steps, each group of cavities whose footprints
  * sum to at most this advances through all its steps before the next group,
- * so its populations stay in the last-level cache. */
+ * so its populations stay in the last-level cache.  A cavity whose footprint
+ * exceeds it steps on the single-cavity path (as lbm_step would) instead.
+ * LBM_EINVAL below 1 MiB. */
 int lbm_set_group_bytes(lbm_ctx *c, size_t bytes);
 /* Diagnostics of the current state.  Blocks.  Returns LBM_EUNSTABLE (with
  * *out filled) when a population is not finite. */

@@ -589,16 +589,21 @@ void free_batch(lbm_ctx *c) {
   b.cav_cap = b.tile_cap = b.hdr_cap = 0;
 }
 
-// Tile lists of every resident slot, grouped by cache group then precision.
-// The device buffers only grow, so a captured graph survives membership
-// changes that keep the group shape.
+// A cavity larger than the cache-group capacity gains nothing from sharing
+// launches (it would form a group of its own, too large for the cache); it
+// steps on the single-cavity path, whose kernels take the whole device.
+bool solo_slot(const lbm_ctx *c, const Slot &s) { return s.lay.total > c->group_bytes; }
+
+// Tile lists of every resident slot that is not solo, grouped by cache group
+// then precision.  The device buffers only grow, so a captured graph
+// survives membership changes that keep the group shape.
 int rebuild_batch(lbm_ctx *c) {
   Batch &b = c->batch;
   b.members.clear();
   for (int i = 0; i < (int)c->slots.size(); ++i)
-    if (c->slots[i].used) b.members.push_back(i);
+    if (c->slots[i].used && !solo_slot(c, c->slots[i])) b.members.push_back(i);
   // greedy packing in slot order: a group closes when the next cavity would
-  // overflow the capacity (a cavity larger than the capacity gets its own)
+  // overflow the capacity
   std::vector<int> group_of(b.members.size(), 0);
   int ngroups = b.members.empty() ? 0 : 1;
   size_t acc = 0;
@@ -775,11 +780,16 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
     if (rc != LBM_OK) return rc;
   }
   std::vector<int64_t> left(c->slots.size(), 0);
+  for (size_t j = 0; j < ids.size(); ++j) left[ids[j]] += n[j];
+  // solo cavities on the single-cavity path (stream-ordered like the rest)
+  for (size_t id = 0; id < left.size(); ++id)
+    if (left[id] > 0 && solo_slot(c, c->slots[id])) {
+      int rc = step_slot(c, c->slots[id], left[id]);
+      if (rc != LBM_OK) return rc;
+      left[id] = 0;
+    }
   int64_t most = 0;
-  for (size_t j = 0; j < ids.size(); ++j) {
-    left[ids[j]] += n[j];
-    most = std::max(most, left[ids[j]]);
-  }
+  for (int64_t v : left) most = std::max(most, v);
   if (most == 0) return LBM_OK;
   // recorded diagnostics need per-step hooks: those slots step on their own
   bool reports = false;

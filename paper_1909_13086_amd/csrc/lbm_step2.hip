@@ -488,11 +488,12 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 // third step (level 3) of the owned rows, which is stored.  FP32 keeps both
 // windows in registers and stages rows through LDS as above (walk3_staged);
 // FP64, whose two windows would exceed the register file, keeps the level-2
-// window in LDS and loads rows directly (walk3_ring).  Level 2 runs on every lane; only lanes 1 .. 62 hold
-// correct values there, which is all level 3 of the owned lanes reads.  Rows
-// outside the cavity give values that no owned cell uses (their links are
-// reflected at the wall).  Each level is the single-step update, so a launch
-// equals three single two-lattice steps bit for bit.
+// window in LDS and loads rows directly (walk3_ring).  Level 2 runs on every
+// lane; only lanes 1 .. 62 hold correct values there, which is all level 3
+// of the owned lanes reads.  Rows outside the cavity give values that no
+// owned cell uses (their links are reflected at the wall).  Each level is the
+// single-step update, so a launch equals three single two-lattice steps bit
+// for bit.
 //
 // Iteration y of the walk (direction D) computes level 1 of row y+2D, level 2
 // of row y+D and level 3 of row y, then slides both windows by one row.  With

@@ -86,15 +86,20 @@ def test_unstable_request_fails_alone(P):
         assert r["stats"]["total_H"] == want["total_H"]
 
 
-def test_step_many_uneven_counts_equal_solo(P):
+@pytest.mark.parametrize("group_bytes", [2 << 20, 1 << 20])
+def test_step_many_uneven_counts_equal_solo(P, group_bytes):
+    """Batched steps with uneven counts over several cache groups (2 MiB), and
+    with the two in-place cavities larger than a group (1 MiB), which then
+    step on the single-cavity path beside the batched one."""
     import numpy as np
+    print(f"case step_many uneven counts, groups of {group_bytes} B", flush=True)
     cases = [dict(cavity(128, 64, Ra=1e5), precision=P.LBM_FP64),
              dict(cavity(192, 96, Ra=1e6, heater_center=0.3), precision=P.LBM_FP32_SHIFTED),
              dict(cavity(64, 32, Ra=1e7), precision=P.LBM_FP64, pattern=P.LBM_PATTERN_AB)]
     counts = [131, 57, 200]
     with P.Context(device=0, max_slots=4) as ctx:
         ctx.set_graph_chunk(25)
-        ctx.set_group_bytes(2 << 20)  # several cache groups
+        ctx.set_group_bytes(group_bytes)
         slots = [ctx.add(c) for c in cases]
         ctx.step_many(slots, counts)
         got = [ctx.state_save(s) for s in slots]
