@@ -224,10 +224,11 @@ enum {
   LBM_LAUNCH_XCD_BANDS = 1,  /* each of the 8 XCDs gets a contiguous band of tiles */
   LBM_LAUNCH_NONTEMPORAL = 2, /* population loads/stores bypass cache retention */
   LBM_LAUNCH_ALTERNATE = 4,  /* tiles walked backwards on every other step */
-  LBM_LAUNCH_ZIGZAG = 8,     /* two-step kernel: odd row segments walked downwards,
+  LBM_LAUNCH_ZIGZAG = 8,     /* fused kernels: odd row segments walked downwards,
                                 so neighbouring segments share halo rows in the L2 */
   LBM_LAUNCH_STAGED = 16     /* two-step kernel: rows copied into LDS one row ahead
-                                by asynchronous global-to-LDS loads */
+                                by asynchronous global-to-LDS loads (three-step
+                                kernels stage in FP32 and not in FP64 regardless) */
 };
 /* Tile of the single-cavity step kernels for a precision: bx threads along x
  * (multiple of 64), by rows per block (bx*by <= 256), cpl rows per lane (1, 2
