@@ -109,3 +109,14 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(P.LbmError) as ei:
         P.lbm_create(0, None, 0, 1)
     assert ei.value.code == P.LBM_EDEVICE
+
+
+def test_context_calls_reject_a_null_context():
+    """Calls on a context return LBM_EINVAL for a NULL context (no GPU needed)."""
+    import ctypes
+    lib = P.lib()
+    n, seg = ctypes.c_int(), ctypes.c_int()
+    assert lib.lbm_slot_fusion(None, 0, ctypes.byref(n), ctypes.byref(seg)) == P.LBM_EINVAL
+    assert lib.lbm_get_fusion(None, 0, ctypes.byref(n), ctypes.byref(seg)) == P.LBM_EINVAL
+    assert lib.lbm_set_fusion(None, 0, 3, 4) == P.LBM_EINVAL
+    assert lib.lbm_set_group_bytes(None, 1 << 30) == P.LBM_EINVAL
