@@ -49,10 +49,14 @@ def log(msg):
 
 
 def kernel_hash(path):
+    """sha256 of the path's kernel sources and of the build script (its
+    compiler flags shape the kernel too)."""
     h = hashlib.sha256()
     for f in PATHS[path]["src"]:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1909_13086_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()
 
 
