@@ -250,7 +250,7 @@ FUSED_GEOMS = GEOMS + [(130, 70, 0, 0, 0.4, 0.3), (200, 37, 1, 1, 0.5, 0.25), (6
 @pytest.mark.parametrize("geom", FUSED_GEOMS, ids=[f"{g[0]}x{g[1]}p{g[2]}{g[3]}" for g in FUSED_GEOMS])
 @pytest.mark.parametrize("prec,seg,steps", [(0, 8, 2), (0, 16, 7), (1, 32, 6), (0, 32, 13), (1, 8, 5),
                                              (0, 6, 4), (1, 5, 3), (0, 1, 2), (0, 3, 5), (1, 64, 4)])
-def test_two_step_kernel_equals_single_steps(P, geom, prec, seg, steps):
+def test_fused_kernels_equal_single_steps(P, geom, prec, seg, steps):
     nx, ny, px, py, hc, hw = geom
     case = dict(cavity(nx, ny, periodic_x=px, periodic_y=py, heater_center=hc, heater_width=hw,
                        param_mode=1, nu=0.04, alpha=0.06, gbeta=3e-3, latent=0.8, Tm=0.1, Th=0.9,
@@ -278,7 +278,7 @@ def test_two_step_kernel_equals_single_steps(P, geom, prec, seg, steps):
 
 
 @pytest.mark.parametrize("chunk", [7, 10])
-def test_two_step_kernel_in_graphs_and_with_reports(P, chunk):
+def test_fused_kernels_in_graphs_and_with_reports(P, chunk):
     case = dict(small_cavity("distinct"), pattern=P.LBM_PATTERN_AB)
     f0, g0 = _random_state(31, 128, 64)
     res = []

@@ -71,7 +71,7 @@ def test_melting_cavity_matches_oracle(P, model, precision):
 
 
 @pytest.mark.parametrize("model", MODELS)
-def test_two_step_and_batched_paths_equal_single_steps(P, model):
+def test_fused_and_batched_paths_equal_single_steps(P, model):
     """Two-lattice launches of two and three steps (rows staged and direct)
     and batched launches of mixed solid models give the single-step results
     bit for bit."""
