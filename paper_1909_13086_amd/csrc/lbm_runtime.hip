@@ -623,8 +623,9 @@ int rebuild_batch(lbm_ctx *c) {
   };
   // Segment rows of each fused launch.  While the fusion is the default they
   // balance the launch: its wavefronts (one per segment) take segments in
-  // passes of step2_batch_grid x 2, and a segment of seg rows costs about
-  // (kind + 1) seg + kind (kind + 1) collisions per row, so the rows that
+  // passes of step2_batch_grid x 2, and a segment of seg rows advanced by
+  // kind + 1 steps costs each lane (kind + 1) seg + kind (kind + 1)
+  // collisions (the halo rows of every level included), so the rows that
   // minimise passes x cost are taken (a launch of few segments prefers short
   // ones, one just above a full pass longer ones).
   const int64_t wave_slots = (int64_t)lbm::step2_batch_grid(c->num_cus) * 2;
