@@ -3,16 +3,20 @@
 Workload (the single-GPU configuration the metric is quoted on): one
 2048x1024 D2Q9 cavity, FP64, Ra = 1e8, Pr = 1, Ste = 1, heater centred with
 width W/4, starting all solid at Tm; flow and enthalpy populations advanced by
-the fused collide-and-stream kernel on two lattices, two time steps per launch
-(--path aa: the in-place kernel, one step per launch), diagnostics (melt
-fraction, Nusselt number, enthalpy budget) reduced on the device every 100
-steps.  A "step" is one time step of that whole path.  Inputs are synthetic
-and resident in HBM before timing starts.
+the fused collide-and-stream kernel on two lattices, three time steps per
+launch (--path ab2: two steps per launch; --path aa: the in-place kernel, one
+step per launch), diagnostics (melt fraction, Nusselt number, enthalpy
+budget) reduced on the device every 100 steps.  A "step" is one time step of
+that whole path.  Inputs are synthetic and resident in HBM before timing
+starts.
 
 Printed: one JSON line with MLUPS (10^6 lattice updates per second, one update
-= one cell's f and g advanced one step), the roofline of the step kernel, the
-oracle timed on the host cores, and the in-place, FP32-shifted, 4096x2048,
-batched and served variants.
+= one cell's f and g advanced one step), the roofline of the step kernel
+(bytes a launch must move: the 18 populations of every cell read once from one
+lattice and written once to the other, whatever the steps per launch), the
+oracle timed on the host cores, the small-cavity solve latency, the FP32
+error against FP64, and the in-place, FP32-shifted, 4096x2048, batched and
+served variants.
 """
 import argparse
 import hashlib
@@ -26,7 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-BYTES_PER_LU = {0: 288, 1: 144}  # 18 populations read + written, FP64 / FP32
+# 18 populations read + written per cell and launch, FP64 / FP32: one lattice
+# update for a one-step launch, and still the bytes a fused launch must move
+BYTES_PER_LU = {0: 288, 1: 144}
 REPORT_EVERY = 100
 # per path: kernel name, sources (a change to any invalidates stored counter
 # traffic), counter summary, steps per launch
@@ -132,17 +138,29 @@ def run_cavity(P, path, steps, warmup, report_every=REPORT_EVERY, graph_chunk=0,
     kms = time_steps(P, ctx, slot2, k2)
     ctx.close()
     pattern = PATHS[path]["pattern"] + (f", {seg}-row segments" if path != "aa" else "")
+    # diagnostics recorded inside the timed steps (warmup + 1 .. warmup + steps)
+    in_window = sum(1 for e in series if warmup < e["step"] <= warmup + steps)
     return dict(case=case, cells=cells, ms=ms, wall=wall, stats=st, series=series, pattern=pattern,
-                launch_ms=kms / k2 * per, launches=k2 // per, steps_per_launch=per)
+                launch_ms=kms / k2 * per, launches=k2 // per, steps_per_launch=per, reports_in_window=in_window)
 
 
 def roofline(path, m):
-    alg = BYTES_PER_LU[0] * m["cells"] * m["steps_per_launch"]
-    achieved = alg / (m["launch_ms"] * 1e-3) / 1e9
+    """HBM roofline of the path's step kernel.  A launch, one step or a fused
+    two or three, must read every cell's 18 populations once and write them
+    once (the per-column strip flux adds 16 B per column): that is the
+    algorithmic byte count per launch, so `frac` is at most 1.  The per-step
+    rate (288 B per lattice update over the time per step) is reported apart
+    as `effective_gbs`; for a fused launch it exceeds the bytes moved."""
+    alg = BYTES_PER_LU[0] * m["cells"] + 16 * m["case"]["nx"]
+    sec = m["launch_ms"] * 1e-3
+    achieved = alg / sec / 1e9
+    traffic = measured_traffic(path)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(path),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_over_algorithmic": round(traffic / alg, 4) if traffic else None,
             "kernel": PATHS[path]["kernel"], "kernel_avg_us": round(m["launch_ms"] * 1e3, 2),
-            "steps_per_launch": m["steps_per_launch"], "algorithmic_bytes_per_launch": alg}
+            "steps_per_launch": m["steps_per_launch"], "algorithmic_bytes_per_launch": alg,
+            "effective_gbs": round(BYTES_PER_LU[0] * m["cells"] * m["steps_per_launch"] / sec / 1e9, 1)}
 
 
 def in_place_variant(P, steps):
@@ -267,6 +285,76 @@ def batched_variant(P, steps, chunk=100, pattern=None):
     return res
 
 
+def small_cavity_solves(P, repeats=20, steps=2000):
+    """The 128x64 FP64 cavity (Ra 1e4, literal rates k0 = k2 = 1) solved as a
+    request: set up from all solid, 2000 steps, reduced.  Time to result of
+    `repeats` solves after one warm-up solve (p50 / p99), with plain launches
+    and with 100-step captured graphs (captured anew for each solve), and the
+    device time per step.  The default launches apply (two lattices; an FP64
+    cavity this small takes two steps per launch)."""
+    import numpy as np
+    from btrirt_workloads import small_cavity
+    case = dict(small_cavity("literal"), pattern=P.LBM_PATTERN_AB)
+    out = {}
+    for chunk, name in ((0, "plain_launches"), (100, "graphs_100")):
+        ctx = P.Context(device=0, max_slots=2)
+        ctx.set_graph_chunk(chunk)
+        times, phi = [], None
+        for k in range(repeats + 1):
+            t0 = time.perf_counter()
+            s = ctx.add(case)
+            ctx.step(s, steps)
+            st = ctx.reduce(s)
+            el = time.perf_counter() - t0
+            fuse = ctx.slot_fusion(s)
+            ctx.release(s)
+            phi = st["melt_fraction"]
+            if k > 0:
+                times.append(el)
+        s = ctx.add(case)
+        ctx.step(s, 100)
+        ms = time_steps(P, ctx, s, steps)
+        ctx.close()
+        out[name] = dict(p50_ms=round(float(np.percentile(times, 50)) * 1e3, 3),
+                         p99_ms=round(float(np.percentile(times, 99)) * 1e3, 3),
+                         us_per_step=round(ms * 1e3 / steps, 3), steps_per_launch=fuse[0], segment_rows=fuse[1])
+    out.update(workload="128x64 FP64, Ra 1e4, k0 = k2 = 1, 2000 steps from all solid", repeats=repeats,
+               melt_fraction=phi)
+    log(f"small-cavity solves: {out}")
+    return out
+
+
+def fp32_error(P, times=(5000, 10000, 20000)):
+    """The FP32-shifted variant of the small cavity (literal rates) against
+    the same cavity in FP64, both on the GPU (the FP64 path equals the oracle
+    to 1e-10 in the tests), at 5k, 10k and 20k steps: Linf of the liquid
+    fraction field, |d melt fraction| and |d Nu|/Nu; in place and on two
+    lattices with three steps per launch."""
+    from btrirt_workloads import small_cavity
+    out = {}
+    for pattern, name in ((P.LBM_PATTERN_AA, "in_place"), (P.LBM_PATTERN_AB, "three_step")):
+        ctx = P.Context(device=0, max_slots=2)
+        if pattern == P.LBM_PATTERN_AB:
+            ctx.set_fusion(0, 3, 4)
+            ctx.set_fusion(1, 3, 6)
+        s64 = ctx.add(dict(small_cavity("literal"), pattern=pattern))
+        s32 = ctx.add(dict(small_cavity("literal"), pattern=pattern, precision=P.LBM_FP32_SHIFTED))
+        rows, done = [], 0
+        for t in times:
+            ctx.step(s64, t - done)
+            ctx.step(s32, t - done)
+            done = t
+            a, b = ctx.reduce(s64), ctx.reduce(s32)
+            fa, fb = ctx.fields(s64, P.LBM_FIELD_FL)["fl"], ctx.fields(s32, P.LBM_FIELD_FL)["fl"]
+            rows.append(dict(step=t, linf_fl=float(abs(fa - fb).max()),
+                             dphi=abs(a["melt_fraction"] - b["melt_fraction"]),
+                             dnu_rel=abs(a["nusselt"] - b["nusselt"]) / abs(a["nusselt"])))
+        ctx.close()
+        out[name] = rows
+    log(f"fp32 vs fp64: {out}")
+    return out
+
+
 def serving_study(P, pattern):
     """The full serving workload (256 seeded Poisson requests at 20/s, sizes
     256x128 ... 2048x1024, 1000-50000 steps, FP64 / FP32-shifted 50/50, 16 GB
@@ -287,11 +375,18 @@ def serving_study(P, pattern):
     return dict(full=full, at_70_percent=at70)
 
 
-def cpu_baseline(target_s):
+def cpu_baseline(target_s, single_steps=100):
     """The FP64 oracle on the host cores, on the same 2048x1024 cavity, for
-    as many whole steps as fit in about target_s seconds."""
+    as many whole steps as fit in about target_s seconds, then on one thread
+    for `single_steps` steps.  The oracle's source is compiled here, on the
+    host that times it, at -O3 -march=native (as its plain C with the same
+    floating-point contract), so the figure is that of this machine's cores."""
+    import tempfile
     import oracle
+    from oracle import build as obuild
     from btrirt_workloads import large_cavity
+    tmp = tempfile.mkdtemp(prefix="oracle_native_")
+    oracle.use_library(obuild.build_native(tmp))
     case = large_cavity()
     o = oracle.Oracle(oracle.case_from_dict(case)).init_solid()
     o.step(1)
@@ -307,20 +402,21 @@ def cpu_baseline(target_s):
     mlups = cells * steps / el / 1e6
     threads = oracle.num_threads()
     log(f"cpu oracle: {steps} steps in {el:.1f} s = {mlups:.2f} MLUPS on {threads} threads")
-    # the same on one thread, for a few seconds
+    # the same on one thread
     oracle.set_threads(1)
     t0, steps1 = time.perf_counter(), 0
-    while steps1 < 2 or time.perf_counter() - t0 < 0.3 * target_s:
-        o.step(1)
-        steps1 += 1
+    for _ in range(single_steps // 10):
+        o.step(10)
+        steps1 += 10
     el1 = time.perf_counter() - t0
     oracle.set_threads(threads)
     mlups1 = cells * steps1 / el1 / 1e6
     log(f"cpu oracle, one thread: {steps1} steps in {el1:.1f} s = {mlups1:.2f} MLUPS")
     return dict(value=round(mlups, 3), unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"2048x1024 FP64 cavity, {steps} steps after one warm-up step "
-                       f"({el:.1f} s, OpenMP over rows)",
-                single_thread_value=round(mlups1, 3), single_thread_steps=steps1)
+                       f"({el:.1f} s, OpenMP over rows; oracle built -O3 -march=native on this host)",
+                single_thread_value=round(mlups1, 3), single_thread_steps=steps1,
+                single_thread_seconds=round(el1, 1))
 
 
 def heater_study(P, fo_end, precision, every_fo=0.005):
@@ -416,6 +512,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true", help="only the main workload")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving runs (about two minutes)")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
     ap.add_argument("--only", choices=["fp32", "batched", "batched_two_step", "serving", "serving_two_step",
                                        "serving_study", "sizes"],
@@ -483,7 +580,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single cavity 2048x1024 D2Q9, FP64, Ra=1e8 Pr=1 Ste=1, heater W/4 centred, "
                                "from all-solid at Tm; diagnostics every 100 steps",
-                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": m["pattern"]},
+                   "nx": 2048, "ny": 1024, "precision": "fp64", "pattern": m["pattern"],
+                   "reports_in_timed_window": m["reports_in_window"]},
         "roofline": roofline(path, m),
         "melt_fraction": m["stats"]["melt_fraction"],
         "nusselt": m["stats"]["nusselt"],
@@ -494,11 +592,12 @@ def main():
             out["in_place_aa"] = in_place_variant(P, max(1000, args.steps // 4))
         out["fp32_shifted"] = fp32_variant(P, max(500, args.steps // 4), path)
         out["hbm_bound_4096x2048"] = hbm_bound_variant(P)
+        out["small_cavity_solve"] = small_cavity_solves(P)
+        out["fp32_vs_fp64"] = fp32_error(P)
         out["batched"] = batched_variant(P, 2000)
         out["batched_two_step"] = batched_variant(P, 2000, pattern=P.LBM_PATTERN_AB)
-        from paper_1909_13086_amd import serve
-        out["serving"] = serve.bench_serving(P)
-        out["serving_two_step"] = serve.bench_serving(P, pattern=P.LBM_PATTERN_AB)
+        if not args.no_serving:
+            out["serving"] = serving_study(P, P.LBM_PATTERN_AB)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

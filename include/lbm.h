@@ -30,6 +30,10 @@
  *   - Work is ordered on the context's HIP stream.  lbm_step only enqueues;
  *     lbm_reduce, lbm_fields, lbm_series, lbm_state_* and lbm_sync block until
  *     the stream has drained.  A context is not thread-safe.
+ *   - A batched launch whose device work list is inconsistent (a bookkeeping
+ *     fault of the library, never expected) advances nothing and raises a
+ *     device error word; the next blocking call (or the next chunk of
+ *     lbm_step_many) returns LBM_EDEVICE and clears it.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -100,7 +104,12 @@ typedef struct {
   double Ra, Pr, Ste, Ma;   /* dimensionless mode */
   double nu, alpha, gbeta, latent; /* lattice mode */
   double Cp, Th, Tm, rho0;
-  double heater_center, heater_width; /* strip centre C and width D as fractions of nx */
+  double heater_center, heater_width; /* strip centre C and width D as fractions of nx
+                                       (Sec. 3.2); cell x is heated when its centre x + 1/2
+                                       lies in [(C - D/2) nx, (C + D/2) nx].  A strip that
+                                       reaches past a side wall is clipped to the cavity
+                                       (only its cells inside are heated); width 0 or a
+                                       periodic y direction means no strip. */
   double k0_g, k2_g, k0_f, k1_f;
   double T0, gauss_amp, gauss_sigma; /* LBM_INIT_LIQUID_T0 / LBM_INIT_GAUSSIAN */
   int32_t solid_model;      /* LBM_SOLID_*: how the solid holds the flow still */
@@ -191,9 +200,14 @@ int lbm_set_group_bytes(lbm_ctx *c, size_t bytes);
 /* Diagnostics of the current state.  Blocks.  Returns LBM_EUNSTABLE (with
  * *out filled) when a population is not finite. */
 int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out);
-/* Macroscopic fields of the current state: for each bit of mask, in the order
- * T, fl, H, ux, uy, rho, one nx*ny plane of doubles into host; n is the
- * capacity of host in doubles.  Blocks. */
+/* Macroscopic fields of the current state (Sec. 2): T and fl from the total
+ * enthalpy H = sum g_i through H = Cp T + fl L with melting at Tm (below
+ * Eq. (1)); the velocity u = fl (j + F/2)/rho0 of the solid-phase reading in
+ * use (u as defined for LBM_SOLID_DARCY / LBM_SOLID_PBB above) and rho = sum f_i.
+ * For each bit of mask, in the order T, fl, H, ux, uy, rho, one nx*ny plane
+ * of doubles (row-major, y = 0 the heated wall) into host; n is the capacity
+ * of host in doubles.  LBM_EINVAL for an empty mask or a short buffer;
+ * LBM_ENOMEM when the device staging buffer cannot grow.  Blocks. */
 int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n);
 
 /* Records diagnostics every `every` steps into a device ring of `capacity`
@@ -216,7 +230,15 @@ int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n);
  * from it reproduces the uninterrupted run bit for bit.  Both block. */
 size_t lbm_checkpoint_bytes(lbm_ctx *c, int slot);
 int lbm_checkpoint_save(lbm_ctx *c, int slot, void *host, size_t n);
+/* Every check (header, embedded case derived as lbm_set_case would, its
+ * precision, pattern and region size against the header and the slot) runs
+ * before anything is copied: on LBM_EINVAL the slot is unchanged. */
 int lbm_checkpoint_load(lbm_ctx *c, int slot, const void *host, size_t n);
+/* Host-only, needs no GPU: validates a checkpoint of n bytes as
+ * lbm_checkpoint_load does (without the slot comparison) and returns its case
+ * and step counter (either output may be NULL).  LBM_EINVAL with a message
+ * for a corrupt, truncated or inconsistent checkpoint. */
+int lbm_checkpoint_info(const void *host, size_t n, lbm_case *cs, int64_t *step);
 
 /* ---- execution control ---------------------------------------------------- */
 

@@ -109,6 +109,14 @@ def lib():
     return _LIB
 
 
+def use_library(path):
+    """Loads the oracle from another build of the same source (e.g. one
+    compiled for the host's instruction set) for the rest of the process."""
+    global _LIB
+    _LIB = load_library(path)
+    return _LIB
+
+
 def _ptr(a):
     return a.ctypes.data_as(_dp)
 

@@ -24,5 +24,18 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_native(dest_dir: str, verbose: bool = False) -> str:
+    """The same source built at -O3 for the host's own instruction set, into
+    dest_dir (for timing the oracle on the machine that runs it; a binary
+    built for one CPU is never shipped to another)."""
+    out = os.path.join(dest_dir, "libbtrirt_oracle_native.so")
+    flags = [f for f in CFLAGS if f != "-O2"] + ["-O3", "-march=native"]
+    cmd = ["gcc", *flags, SRC, "-o", out, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)

@@ -34,7 +34,8 @@ EXPORTS = (
     "lbm_fields", "lbm_set_report", "lbm_series", "lbm_state_load", "lbm_state_save",
     "lbm_set_launch", "lbm_get_launch", "lbm_set_graph_chunk", "lbm_autotune", "lbm_sync",
     "lbm_stream", "lbm_slot_info", "lbm_slot_fusion", "lbm_step_many", "lbm_set_group_bytes",
-    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_set_fusion", "lbm_get_fusion",
+    "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_checkpoint_info",
+    "lbm_set_fusion", "lbm_get_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
     "lbm_server_request", "lbm_server_summary", "lbm_server_on_finish",
 )
@@ -112,15 +113,28 @@ def make_case(d=None, **kw):
 
 _L = None
 _dp = ctypes.POINTER(ctypes.c_double)
+_BUILD_HINT = "`python -c 'import __graft_entry__ as g; g.build()'`"
+
+
+def _newest_source():
+    """Newest modification time among the library's sources and headers."""
+    srcs = [os.path.join(_HERE, "csrc", f) for f in os.listdir(os.path.join(_HERE, "csrc"))]
+    inc = os.path.join(os.path.dirname(_HERE), "include")
+    srcs += [os.path.join(inc, f) for f in os.listdir(inc)]
+    srcs.append(os.path.join(_HERE, "build.py"))
+    return max(os.path.getmtime(f) for f in srcs if os.path.isfile(f))
 
 
 def lib():
-    """The loaded library.  Raises if it has not been built."""
+    """The loaded library.  Raises if it has not been built, or if a source
+    is newer than the built library (a stale binary would run other code than
+    the sources show)."""
     global _L
     if _L is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+            raise ImportError(f"{LIB_PATH} is missing: build it with {_BUILD_HINT}")
+        if os.path.getmtime(LIB_PATH) < _newest_source():
+            raise ImportError(f"{LIB_PATH} is older than its sources: rebuild it with {_BUILD_HINT}")
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         sig = {
@@ -157,6 +171,8 @@ def lib():
             "lbm_checkpoint_bytes": (ctypes.c_size_t, [vp, ctypes.c_int]),
             "lbm_checkpoint_save": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t]),
             "lbm_checkpoint_load": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t]),
+            "lbm_checkpoint_info": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.POINTER(lbm_case),
+                                                   ctypes.POINTER(ctypes.c_int64)]),
             "lbm_stream": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
             "lbm_slot_info": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)]),
@@ -298,6 +314,15 @@ def lbm_checkpoint_save(ctx, slot):
 def lbm_checkpoint_load(ctx, slot, blob):
     buf = ctypes.create_string_buffer(bytes(blob), len(blob))
     _check(lib().lbm_checkpoint_load(ctx, int(slot), ctypes.cast(buf, ctypes.c_void_p), len(blob)))
+
+
+def lbm_checkpoint_info(blob):
+    """(case, step) of a checkpoint, validated on the host (no GPU needed)."""
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    cs, step = lbm_case(), ctypes.c_int64()
+    _check(lib().lbm_checkpoint_info(ctypes.cast(buf, ctypes.c_void_p), len(blob), ctypes.byref(cs),
+                                     ctypes.byref(step)))
+    return cs, step.value
 
 
 # ---- execution control --------------------------------------------------------

@@ -20,9 +20,12 @@ __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ c
                                                     const BatchTile *__restrict__ tiles,
                                                     const int32_t *__restrict__ hdr,
                                                     int tile_cap, int tile_rows,
-                                                    int launch_index) {
+                                                    int launch_index, int32_t *__restrict__ err) {
   const int first = hdr[0], ntiles = hdr[1];
-  if (first < 0 || ntiles <= 0 || first > tile_cap - ntiles) return;
+  if (!batch_header_ok(first, ntiles, tile_cap)) {
+    if (threadIdx.x == 0 && threadIdx.y == 0) *err = kErrBatchHeader;
+    return;
+  }
   const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
   const int nbx = (gridDim.x - xcd + kXcds - 1) / kXcds;
   const int t0 = (int)((int64_t)ntiles * xcd / kXcds);
@@ -48,17 +51,17 @@ __global__ __launch_bounds__(256) void k_step_batch(const CavDev *__restrict__ c
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
                              const int32_t *hdr_dev, int tile_cap, int precision, int model,
                              int tile_bx, int tile_rows, int launch_index, int grid,
-                             hipStream_t s) {
+                             int32_t *err_dev, hipStream_t s) {
   const int by = 256 / tile_bx;
   const dim3 block(tile_bx, by < 1 ? 1 : by);
   with_model(model, [&](auto m) {
     constexpr int M = decltype(m)::value;
     if (precision == 0)
       hipLaunchKernelGGL((k_step_batch<double, double, M>), dim3(grid), block, 0, s, cavs_dev,
-                         tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+                         tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index, err_dev);
     else
       hipLaunchKernelGGL((k_step_batch<float, float, M>), dim3(grid), block, 0, s, cavs_dev,
-                         tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index);
+                         tiles_dev, hdr_dev, tile_cap, tile_rows, launch_index, err_dev);
     return 0;
   });
   return hipGetLastError();

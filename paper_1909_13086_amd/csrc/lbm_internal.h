@@ -87,6 +87,17 @@ struct StatsDev {
   double pad;
 };
 
+// Device error word of a context: set by a batched kernel whose work-list
+// header is empty or out of range (a host bookkeeping fault); the launch then
+// advances nothing.
+constexpr int32_t kErrBatchHeader = 1;
+
+// The header {first, count} of a batched launch addresses items [first,
+// first + count) of a list of cap entries.
+__device__ __forceinline__ bool batch_header_ok(int first, int count, int cap) {
+  return first >= 0 && count > 0 && first <= cap - count;
+}
+
 constexpr int kRedBlocks = 512;   // fixed grid of the reduction (deterministic order)
 constexpr int kRedThreads = 256;
 
@@ -101,26 +112,29 @@ hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hi
 // FP64 keeps its level-2 window there and loads rows directly.
 hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
-// entries (the kernel ignores a header that points outside them).
+// entries.  A header that is empty or points outside them advances nothing
+// and sets *err_dev to kErrBatchHeader, which the host reports as an error.
 // model: the solid model shared by every cavity of the tile list (kSolid*).
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
                              const int32_t *hdr_dev, int tile_cap, int precision, int model,
                              int tile_bx, int tile_rows, int launch_index, int grid,
-                             hipStream_t s);
+                             int32_t *err_dev, hipStream_t s);
 // Batched two-step launch over wavefront items {cavity, strip origin x0,
 // segment origin y0, segment index} of two-lattice cavities: launch j
 // advances cavity c by two steps while 2 j + 2 <= active_steps(c), by one
 // step when 2 j + 1 == active_steps(c), else leaves it.
 hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
                               const int32_t *hdr_dev, int item_cap, int precision, int model,
-                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s);
+                              const LaunchCfg &cfg, int launch_index, int grid, int32_t *err_dev,
+                              hipStream_t s);
 // Batched three-step launch over 60-column strip segments (cfg.seg3 rows):
 // launch j advances cavity c by three steps while 3 j + 3 <= active_steps(c),
 // by the one or two steps left when 3 j < active_steps(c) < 3 j + 3, else
 // leaves it.
 hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
                               const int32_t *hdr_dev, int item_cap, int precision, int model,
-                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s);
+                              const LaunchCfg &cfg, int launch_index, int grid, int32_t *err_dev,
+                              hipStream_t s);
 // Workgroups of a batched two- or three-step launch that fill the device once.
 int step2_batch_grid(int num_cus);
 hipError_t launch_reduce(const CavDev &c, int precision, double *partials, StatsDev *out,

@@ -271,6 +271,8 @@ struct lbm_ctx {
   size_t budget = 0, used = 0;
   std::vector<Slot> slots;
   double *partials = nullptr;
+  int32_t *err_dev = nullptr;      // device error word of the batched kernels (kErrBatchHeader)
+  int32_t *err_host = nullptr;     // pinned copy, read after the stream has drained
   StatsDev *stats_dev = nullptr;
   StatsDev *stats_host = nullptr;  // pinned, 2 entries: current state and state at load
   void *scratch = nullptr;
@@ -289,6 +291,30 @@ int check_slot(lbm_ctx *c, int slot) {
   if (slot < 0 || slot >= (int)c->slots.size() || !c->slots[slot].used)
     return fail(LBM_ESTATE, "slot " + std::to_string(slot) + " is not in use");
   return LBM_OK;
+}
+
+// Copies the device error word behind the work already enqueued (no wait).
+hipError_t enqueue_error_copy(lbm_ctx *c) {
+  return hipMemcpyAsync(c->err_host, c->err_dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+}
+
+// After the stream has drained past an enqueue_error_copy: turns a device error
+// raised by a batched kernel into LBM_EDEVICE and clears the word.
+int take_device_error(lbm_ctx *c) {
+  const int32_t e = *c->err_host;
+  if (e == 0) return LBM_OK;
+  *c->err_host = 0;
+  HIP_TRY(lbm::launch_fill_zero(c->err_dev, sizeof(int32_t), c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return fail(LBM_EDEVICE, "a batched launch found its work-list header empty or out of range "
+                           "and advanced nothing (code " + std::to_string(e) + ")");
+}
+
+// Waits for the stream and reports a device error raised since the last check.
+int sync_checked(lbm_ctx *c) {
+  HIP_TRY(enqueue_error_copy(c));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return take_device_error(c);
 }
 
 int ensure_scratch(lbm_ctx *c, size_t bytes) {
@@ -369,7 +395,8 @@ int reduce_now(lbm_ctx *c, Slot &s, StatsDev *out_host, double *e0) {
                          c->stream));
   HIP_TRY(hipMemcpyAsync(c->stats_host + 1, s.e0_dev, sizeof(StatsDev), hipMemcpyDeviceToHost,
                          c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int rc = sync_checked(c);
+  if (rc != LBM_OK) return rc;
   *out_host = c->stats_host[0];
   *e0 = c->stats_host[1].total_H;
   return LBM_OK;
@@ -717,6 +744,16 @@ int rebuild_batch(lbm_ctx *c) {
       }
     }
   }
+  // every header a launch will read addresses a non-empty range of the list
+  for (int g = 0; g < ngroups; ++g)
+    for (int bit = 0; bit < kLaunchKinds; ++bit) {
+      if (!(b.group_precs[g] & (1 << bit))) continue;
+      const int32_t first = b.hdr_host[(g * kLaunchKinds + bit) * 2];
+      const int32_t count = b.hdr_host[(g * kLaunchKinds + bit) * 2 + 1];
+      if (first < 0 || count <= 0 || (size_t)first + (size_t)count > t || t > b.tile_cap)
+        return fail(LBM_ESTATE, "batched work list inconsistent: header {" + std::to_string(first) + ", " +
+                                    std::to_string(count) + "} over " + std::to_string(t) + " items");
+    }
   if (t > 0)
     HIP_TRY(hipMemcpyAsync(b.tiles_dev, b.tiles_host, t * sizeof(BatchTile),
                            hipMemcpyHostToDevice, c->stream));
@@ -744,7 +781,7 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
             err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev,
                                          b.hdr_dev + hdr_index(g, prec, 0, model), (int)b.tile_cap,
                                          prec, model, kBatchTileX, kBatchTileRows, k,
-                                         batch_grid(c), c->stream);
+                                         batch_grid(c), c->err_dev, c->stream);
     for (int j = 0; j < (chunk + 1) / 2 && err == hipSuccess; ++j)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
         for (int model = 0; model < 3 && err == hipSuccess; ++model)
@@ -754,7 +791,7 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
             err = lbm::launch_step2_batch(b.cavs_dev, b.tiles_dev,
                                           b.hdr_dev + hdr_index(g, prec, 1, model),
                                           (int)b.tile_cap, prec, model, L, j,
-                                          lbm::step2_batch_grid(c->num_cus), c->stream);
+                                          lbm::step2_batch_grid(c->num_cus), c->err_dev, c->stream);
           }
     for (int j = 0; j < (chunk + 2) / 3 && err == hipSuccess; ++j)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
@@ -765,7 +802,7 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
             err = lbm::launch_step3_batch(b.cavs_dev, b.tiles_dev,
                                           b.hdr_dev + hdr_index(g, prec, 2, model),
                                           (int)b.tile_cap, prec, model, L, j,
-                                          lbm::step2_batch_grid(c->num_cus), c->stream);
+                                          lbm::step2_batch_grid(c->num_cus), c->err_dev, c->stream);
           }
   }
   return err;
@@ -806,7 +843,11 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
   const int cap = c->graph_chunk > 0 ? c->graph_chunk : 64;
   while (most > 0) {
     const int chunk = (int)std::min<int64_t>(most, cap);
-    HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffer reuse
+    {
+      // staging buffer reuse; a device error of the previous chunk surfaces here
+      const int rc = sync_checked(c);
+      if (rc != LBM_OK) return rc;
+    }
     for (size_t j = 0; j < b.members.size(); ++j) {
       const int id = b.members[j];
       CavDev d = c->slots[id].dev;
@@ -854,6 +895,7 @@ int step_many(lbm_ctx *c, const std::vector<int> &ids, const std::vector<int64_t
     }
     most -= chunk;
   }
+  HIP_TRY(enqueue_error_copy(c));
   return LBM_OK;
 }
 
@@ -936,8 +978,16 @@ int lbm_create(lbm_ctx **out, int device, void *hip_stream, size_t hbm_budget, i
   if (rc == LBM_OK &&
       (hipMalloc(&c->partials, (size_t)lbm::kRedBlocks * 16 * sizeof(double)) != hipSuccess ||
        hipMalloc(&c->stats_dev, sizeof(StatsDev)) != hipSuccess ||
+       hipMalloc(&c->err_dev, sizeof(int32_t)) != hipSuccess ||
+       hipHostMalloc(&c->err_host, sizeof(int32_t)) != hipSuccess ||
        hipHostMalloc(&c->stats_host, 2 * sizeof(StatsDev)) != hipSuccess))
     rc = fail(LBM_ENOMEM, "cannot allocate reduction scratch");
+  if (rc == LBM_OK) {
+    *c->err_host = 0;
+    if (lbm::launch_fill_zero(c->err_dev, sizeof(int32_t), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = fail(LBM_EDEVICE, "cannot clear the device error word");
+  }
   if (rc != LBM_OK) {
     lbm_destroy(c);
     return rc;
@@ -955,6 +1005,8 @@ void lbm_destroy(lbm_ctx *c) {
   free_batch(c);
   if (c->partials) (void)hipFree(c->partials);
   if (c->stats_dev) (void)hipFree(c->stats_dev);
+  if (c->err_dev) (void)hipFree(c->err_dev);
+  if (c->err_host) (void)hipHostFree(c->err_host);
   if (c->stats_host) (void)hipHostFree(c->stats_host);
   if (c->scratch) (void)hipFree(c->scratch);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1106,8 +1158,7 @@ int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n) {
                              c->stream));
   HIP_TRY(hipMemcpyAsync(host, c->scratch, planes * cells * sizeof(double),
                          hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return sync_checked(c);
 }
 
 int lbm_set_report(lbm_ctx *c, int slot, int64_t every, int32_t capacity) {
@@ -1145,7 +1196,8 @@ int lbm_series(lbm_ctx *c, int slot, lbm_stats *host, int32_t max, int32_t *coun
   if (k == 0) return LBM_OK;
   std::vector<StatsDev> tmp(k);
   StatsDev e0{};
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  rc = sync_checked(c);
+  if (rc != LBM_OK) return rc;
   HIP_TRY(hipMemcpy(tmp.data(), s.series, k * sizeof(StatsDev), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(&e0, s.e0_dev, sizeof(StatsDev), hipMemcpyDeviceToHost));
   for (int32_t j = 0; j < k; ++j)
@@ -1184,8 +1236,7 @@ int lbm_state_save(lbm_ctx *c, int slot, double *f, double *g, size_t n) {
   HIP_TRY(lbm::launch_save(s.dev, s.cs.precision, df, dg, c->stream));
   HIP_TRY(hipMemcpyAsync(f, df, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(g, dg, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return sync_checked(c);
 }
 
 int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags) {
@@ -1257,8 +1308,7 @@ int lbm_set_graph_chunk(lbm_ctx *c, int chunk) {
 
 int lbm_sync(lbm_ctx *c) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return sync_checked(c);
 }
 
 int lbm_stream(lbm_ctx *c, void **stream) {
@@ -1569,34 +1619,66 @@ extern "C" int lbm_checkpoint_save(lbm_ctx *c, int slot, void *host, size_t n) {
   return LBM_OK;
 }
 
+namespace {
+
+// Checks a checkpoint on the host without touching any device: header, the
+// embedded case (derived as lbm_set_case would), and the agreement of the
+// header's precision, pattern and region size with that case.
+int validate_checkpoint(const void *host, size_t n, CheckpointHeader *h, lbm_lattice *lat,
+                        Layout *lay) {
+  if (!host || n < sizeof(*h)) return fail(LBM_EINVAL, "checkpoint too short");
+  std::memcpy(h, host, sizeof(*h));
+  if (std::memcmp(h->magic, kMagic, sizeof(kMagic)) != 0 || h->version != 1 ||
+      h->header_bytes != sizeof(*h))
+    return fail(LBM_EINVAL, "not a checkpoint of this library version");
+  if (h->parity != 0 && h->parity != 1) return fail(LBM_EINVAL, "corrupt checkpoint parity");
+  if (h->step < 0) return fail(LBM_EINVAL, "corrupt checkpoint step counter");
+  std::string why;
+  if (derive(&h->cs, lat, why) != LBM_OK) return fail(LBM_EINVAL, "checkpoint case invalid: " + why);
+  if (h->cs.precision != h->precision || h->cs.pattern != h->pattern)
+    return fail(LBM_EINVAL, "checkpoint header and its case disagree on precision or pattern");
+  *lay = layout_of(&h->cs, *lat);
+  if (lay->total != h->region_bytes)
+    return fail(LBM_EINVAL, "checkpoint region of " + std::to_string(h->region_bytes) +
+                                " bytes does not match its case (" + std::to_string(lay->total) + ")");
+  if (n - sizeof(*h) < h->region_bytes) return fail(LBM_EINVAL, "checkpoint truncated");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" int lbm_checkpoint_info(const void *host, size_t n, lbm_case *cs, int64_t *step) {
+  CheckpointHeader h{};
+  lbm_lattice lat;
+  Layout lay;
+  const int rc = validate_checkpoint(host, n, &h, &lat, &lay);
+  if (rc != LBM_OK) return rc;
+  if (cs) *cs = h.cs;
+  if (step) *step = h.step;
+  return LBM_OK;
+}
+
 extern "C" int lbm_checkpoint_load(lbm_ctx *c, int slot, const void *host, size_t n) {
   int rc = check_slot(c, slot);
   if (rc != LBM_OK) return rc;
   Slot &s = c->slots[slot];
   CheckpointHeader h{};
-  if (!host || n < sizeof(h)) return fail(LBM_EINVAL, "checkpoint too short");
-  std::memcpy(&h, host, sizeof(h));
-  if (std::memcmp(h.magic, kMagic, sizeof(kMagic)) != 0 || h.version != 1 ||
-      h.header_bytes != sizeof(h))
-    return fail(LBM_EINVAL, "not a checkpoint of this library version");
-  if (h.cs.nx != s.cs.nx || h.cs.ny != s.cs.ny || h.precision != s.cs.precision ||
-      h.pattern != s.cs.pattern || h.region_bytes != s.lay.total)
+  lbm_lattice lat;
+  Layout lay;
+  rc = validate_checkpoint(host, n, &h, &lat, &lay);
+  if (rc != LBM_OK) return rc;
+  if (h.cs.nx != s.cs.nx || h.cs.ny != s.cs.ny || h.cs.precision != s.cs.precision ||
+      h.cs.pattern != s.cs.pattern || lay.total != s.lay.total)
     return fail(LBM_EINVAL, "checkpoint was taken from a cavity of another size, precision or pattern");
-  if (n < sizeof(h) + h.region_bytes) return fail(LBM_EINVAL, "checkpoint truncated");
-  if (h.parity != 0 && h.parity != 1) return fail(LBM_EINVAL, "corrupt checkpoint parity");
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  // everything is checked: only now does the slot change
+  rc = sync_checked(c);
+  if (rc != LBM_OK) return rc;
   HIP_TRY(hipMemcpyAsync(s.base, static_cast<const char *>(host) + sizeof(h), s.lay.total,
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   // the physics of the restored run is the checkpoint's
-  const lbm_case keep = s.cs;
   s.cs = h.cs;
-  std::string why;
-  if (derive(&s.cs, &s.lat, why) != LBM_OK) {
-    s.cs = keep;
-    (void)derive(&s.cs, &s.lat, why);
-    return fail(LBM_EINVAL, "checkpoint case invalid: " + why);
-  }
+  s.lat = lat;
   s.dev = make_dev(&s.cs, s.lat, s.lay, s.base);
   s.dev.parity = h.parity;
   s.step = h.step;

@@ -749,11 +749,15 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restr
                                                            const BatchTile *__restrict__ items,
                                                            const int32_t *__restrict__ hdr,
                                                            int item_cap, int seg_rows,
-                                                           int launch_index, int order) {
+                                                           int launch_index, int order,
+                                                           int32_t *__restrict__ err) {
   constexpr int waves = STAGED ? kStagedWaves : kDirectWaves;
   __shared__ S lds[STAGED ? waves * 2 * kPlanes * kWave : 1];
   const int first = hdr[0], n = hdr[1];
-  if (first < 0 || n <= 0 || first > item_cap - n) return;
+  if (!batch_header_ok(first, n, item_cap)) {
+    if (threadIdx.x == 0) *err = kErrBatchHeader;
+    return;
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
@@ -815,10 +819,14 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step3_batch(const CavDev *__restr
                                                            const BatchTile *__restrict__ items,
                                                            const int32_t *__restrict__ hdr,
                                                            int item_cap, int seg_rows,
-                                                           int launch_index, int order) {
+                                                           int launch_index, int order,
+                                                           int32_t *__restrict__ err) {
   __shared__ R lds[kStagedWaves * 2 * kPlanes * kWave];
   const int first = hdr[0], n = hdr[1];
-  if (first < 0 || n <= 0 || first > item_cap - n) return;
+  if (!batch_header_ok(first, n, item_cap)) {
+    if (threadIdx.x == 0) *err = kErrBatchHeader;
+    return;
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int xcd = blockIdx.x % kXcds, lb = blockIdx.x / kXcds;
@@ -854,12 +862,13 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step3_batch(const CavDev *__restr
 
 template <typename S, typename R>
 hipError_t dispatch3_batch(const CavDev *cavs, const BatchTile *items, const int32_t *hdr, int item_cap,
-                           int model, const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
+                           int model, const LaunchCfg &cfg, int launch_index, int grid, int32_t *err,
+                           hipStream_t s) {
   if (cfg.seg3 < 1 || cfg.seg3 > kMaxSegmentRows) return hipErrorInvalidValue;
   const int order = cfg.zigzag ? 4 : 0;
   with_model(model, [&](auto m) {
     hipLaunchKernelGGL((k_step3_batch<S, R, decltype(m)::value>), dim3(grid), dim3(kStagedWaves * kWave), 0,
-                       s, cavs, items, hdr, item_cap, cfg.seg3, launch_index, order);
+                       s, cavs, items, hdr, item_cap, cfg.seg3, launch_index, order, err);
     return 0;
   });
   return hipGetLastError();
@@ -868,14 +877,14 @@ hipError_t dispatch3_batch(const CavDev *cavs, const BatchTile *items, const int
 template <typename S, typename R, bool STAGED>
 hipError_t dispatch_batch(const CavDev *cavs, const BatchTile *items, const int32_t *hdr,
                           int item_cap, int model, const LaunchCfg &cfg, int launch_index,
-                          int grid, hipStream_t s) {
+                          int grid, int32_t *err, hipStream_t s) {
   if (cfg.seg < 1 || cfg.seg > kMaxSegmentRows) return hipErrorInvalidValue;
   const int per_block = STAGED ? kStagedWaves : kDirectWaves;
   const int order = cfg.zigzag ? 4 : 0;
   with_model(model, [&](auto m) {
     hipLaunchKernelGGL((k_step2_batch<S, R, STAGED, decltype(m)::value>), dim3(grid),
                        dim3(per_block * kWave), 0, s, cavs, items, hdr, item_cap, cfg.seg,
-                       launch_index, order);
+                       launch_index, order, err);
     return 0;
   });
   return hipGetLastError();
@@ -890,27 +899,29 @@ int step2_batch_grid(int num_cus) {
 
 hipError_t launch_step2_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
                               const int32_t *hdr_dev, int item_cap, int precision, int model,
-                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
+                              const LaunchCfg &cfg, int launch_index, int grid, int32_t *err_dev,
+                              hipStream_t s) {
   if (cfg.staged)
     return precision == 0
                ? dispatch_batch<double, double, true>(cavs_dev, items_dev, hdr_dev, item_cap, model,
-                                                      cfg, launch_index, grid, s)
+                                                      cfg, launch_index, grid, err_dev, s)
                : dispatch_batch<float, float, true>(cavs_dev, items_dev, hdr_dev, item_cap, model,
-                                                    cfg, launch_index, grid, s);
+                                                    cfg, launch_index, grid, err_dev, s);
   return precision == 0
              ? dispatch_batch<double, double, false>(cavs_dev, items_dev, hdr_dev, item_cap, model,
-                                                     cfg, launch_index, grid, s)
+                                                     cfg, launch_index, grid, err_dev, s)
              : dispatch_batch<float, float, false>(cavs_dev, items_dev, hdr_dev, item_cap, model,
-                                                   cfg, launch_index, grid, s);
+                                                   cfg, launch_index, grid, err_dev, s);
 }
 
 hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev,
                               const int32_t *hdr_dev, int item_cap, int precision, int model,
-                              const LaunchCfg &cfg, int launch_index, int grid, hipStream_t s) {
+                              const LaunchCfg &cfg, int launch_index, int grid, int32_t *err_dev,
+                              hipStream_t s) {
   return precision == 0 ? dispatch3_batch<double, double>(cavs_dev, items_dev, hdr_dev, item_cap, model,
-                                                          cfg, launch_index, grid, s)
+                                                          cfg, launch_index, grid, err_dev, s)
                         : dispatch3_batch<float, float>(cavs_dev, items_dev, hdr_dev, item_cap, model,
-                                                        cfg, launch_index, grid, s);
+                                                        cfg, launch_index, grid, err_dev, s);
 }
 
 hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {

@@ -120,3 +120,70 @@ def test_context_calls_reject_a_null_context():
     assert lib.lbm_get_fusion(None, 0, ctypes.byref(n), ctypes.byref(seg)) == P.LBM_EINVAL
     assert lib.lbm_set_fusion(None, 0, 3, 4) == P.LBM_EINVAL
     assert lib.lbm_set_group_bytes(None, 1 << 30) == P.LBM_EINVAL
+
+
+class _CkptHeader(__import__("ctypes").Structure):
+    """Host layout of a checkpoint header (magic, version, header bytes,
+    precision, pattern, parity, step, region bytes, case)."""
+    import ctypes as _c
+    _fields_ = [("magic", _c.c_char * 8), ("version", _c.c_uint32), ("header_bytes", _c.c_uint32),
+                ("precision", _c.c_int32), ("pattern", _c.c_int32), ("parity", _c.c_int32), ("pad", _c.c_int32),
+                ("step", _c.c_int64), ("region_bytes", _c.c_uint64), ("cs", P.lbm_case)]
+
+
+def _blob(case, **over):
+    import ctypes
+    c = P.make_case(case)
+    h = _CkptHeader()
+    h.magic = b"BTRIRTCK"
+    h.version = 1
+    h.header_bytes = ctypes.sizeof(_CkptHeader)
+    h.precision, h.pattern, h.parity, h.step = c.precision, c.pattern, 1, 437
+    h.region_bytes = P.lbm_footprint(c)
+    h.cs = c
+    for k, v in over.items():
+        if k.startswith("cs_"):
+            setattr(h.cs, k[3:], v)
+        else:
+            setattr(h, k, v)
+    return bytes(h) + bytes(h.region_bytes)
+
+
+def test_checkpoint_info_accepts_a_consistent_checkpoint():
+    case = dict(small_cavity("distinct"), pattern=P.LBM_PATTERN_AB)
+    cs, step = P.lbm_checkpoint_info(_blob(case))
+    assert step == 437 and (cs.nx, cs.ny, cs.pattern, cs.k0_g) == (128, 64, P.LBM_PATTERN_AB, 0.8)
+
+
+@pytest.mark.parametrize("over", [
+    dict(magic=b"NOTACKPT"), dict(version=2), dict(parity=2), dict(step=-1),
+    # header and embedded case disagree: an in-place FP64 header over a two-lattice case
+    dict(pattern=P.LBM_PATTERN_AA), dict(precision=P.LBM_FP32_SHIFTED),
+    # embedded case invalid, or of another size than the region
+    dict(cs_k0_g=2.5), dict(cs_nx=0), dict(cs_ny=65), dict(region_bytes=1 << 20),
+])
+def test_checkpoint_info_rejects_an_inconsistent_checkpoint(over):
+    case = dict(small_cavity("distinct"), pattern=P.LBM_PATTERN_AB)
+    with pytest.raises(P.LbmError) as ei:
+        P.lbm_checkpoint_info(_blob(case, **over))
+    assert ei.value.code == P.LBM_EINVAL
+
+
+def test_checkpoint_info_rejects_a_truncated_checkpoint():
+    blob = _blob(small_cavity("eq6"))
+    for n in (0, 50, len(blob) - 1):
+        with pytest.raises(P.LbmError):
+            P.lbm_checkpoint_info(blob[:n])
+
+
+def test_stale_library_is_refused(tmp_path, monkeypatch):
+    """A built library older than a source is not loaded."""
+    import shutil
+    from paper_1909_13086_amd import _lib
+    old = tmp_path / "liblbm.so"
+    shutil.copy(_lib.LIB_PATH, old)
+    os.utime(old, (1, 1))
+    monkeypatch.setattr(_lib, "LIB_PATH", str(old))
+    monkeypatch.setattr(_lib, "_L", None)
+    with pytest.raises(ImportError, match="older than its sources"):
+        _lib.lib()

@@ -1,11 +1,24 @@
 """Batched launch: many cavities of uneven size and precision advance in one
 launch per step (optionally replayed from a captured graph); each cavity's
-result must equal its own solo run bitwise."""
+result must equal its own solo run bitwise, and the oracle's: FP64 cavities
+per population at 1e-13, FP32-shifted ones at 2e-6 (a few units in the last
+place of FP32 values of order one)."""
 import numpy as np
 import pytest
 
 from btrirt_workloads import batch_sweep, cavity
-from tests.test_gpu_parity import _random_state
+from tests.test_gpu_parity import _random_state, oracle_run
+
+FP64_POP_TOL, FP32_POP_TOL = 1e-13, 2e-6
+
+
+def assert_matches_oracle(case, f0, g0, steps, pops):
+    """Populations after `steps` steps from (f0, g0) against the oracle."""
+    o = oracle_run(case, steps, f0, g0)
+    fo, go = o.populations()
+    tol = FP64_POP_TOL if case.get("precision", 0) == 0 else FP32_POP_TOL
+    df, dg = float(np.max(np.abs(pops[0] - fo))), float(np.max(np.abs(pops[1] - go)))
+    assert df <= tol and dg <= tol, (case["nx"], case["ny"], case.get("precision", 0), df, dg)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +71,7 @@ def test_batch_equals_solo_bitwise(P, chunk, steps):
         assert infos[k][0] == n
         want = _solo(P, c, f0, g0, n)
         assert np.array_equal(got[k][0], want[0]) and np.array_equal(got[k][1], want[1]), k
+        assert_matches_oracle(c, f0, g0, n, got[k])
 
 
 def test_batch_membership_changes_keep_results(P):
@@ -138,6 +152,7 @@ def test_fused_batch_uneven_steps_equal_solo(P, fuse, flags, seg, chunk):
         assert np.array_equal(got[k][0][0], want[0][0]) and np.array_equal(got[k][0][1], want[0][1]), k
         for key in ("melt_fraction", "total_H", "heat_in_cum", "heater_q", "budget_residual"):
             assert got[k][1][key] == want[1][key], (k, key)
+        assert_matches_oracle(c, *states[k], n, got[k][0])
 
 
 def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path):

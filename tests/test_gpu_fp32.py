@@ -1,7 +1,11 @@
 """FP32 shifted-population path: populations stored as f_i - w_i rho0 and
 g_i - w_i Cp Tm in FP32, diagnostics reduced in FP64.  Error against the FP64
 oracle is reported per result (liquid-fraction field, melt fraction, Nusselt
-number); the bar is 1e-4 in melt fraction and 0.5 % in Nusselt number."""
+number); the bar is 1e-4 in melt fraction and 0.5 % in Nusselt number.  The
+liquid-fraction field is bounded by FL_LINF: in the mushy cells fl = (H - Cp
+Tm)/L with L = 1 here, so its error is the enthalpy error of the few cells at
+the front, where FP32 rounding of order 1e-7 per step gathers over 20000 steps
+(about 3e-4 observed); the bound leaves a factor of three."""
 import numpy as np
 import pytest
 
@@ -18,13 +22,19 @@ def P():
     return P
 
 
+FL_LINF = 1e-3
+
+
+@pytest.mark.parametrize("pattern", [0, 1], ids=["in_place", "three_step"])
 @pytest.mark.parametrize("variant", ["literal", "eq6"])
-def test_fp32_shifted_small_cavity_to_20k_steps(P, variant):
-    case = dict(small_cavity(variant), precision=P.LBM_FP32_SHIFTED)
-    print(f"case small_cavity[{variant}] FP32 shifted to 20000 steps", flush=True)
+def test_fp32_shifted_small_cavity_to_20k_steps(P, variant, pattern):
+    case = dict(small_cavity(variant), precision=P.LBM_FP32_SHIFTED, pattern=pattern)
+    print(f"case small_cavity[{variant}] FP32 shifted pattern {pattern} to 20000 steps", flush=True)
     o = oracle.Oracle(oracle.case_from_dict(case)).init_solid()
     rows = []
     with P.Context(device=0, max_slots=2) as ctx:
+        if pattern == 1:
+            ctx.set_fusion(P.LBM_FP32_SHIFTED, 3, 6)
         s = ctx.add(case)
         done = 0
         for t in (5000, 10000, 20000):
@@ -41,6 +51,7 @@ def test_fp32_shifted_small_cavity_to_20k_steps(P, variant):
                   f"budget={st['budget_residual']:.2e}", flush=True)
             assert dphi <= 1e-4
             assert dnu <= 5e-3
+            assert fl_err <= FL_LINF
             assert st["finite"] == 1
 
 

@@ -45,15 +45,62 @@ def max_field_err(got, want, names=("H", "T", "fl", "ux", "uy", "rho")):
     return {n: float(np.max(np.abs(got[n] - want[n]))) for n in names}
 
 
+_ORACLE_2000 = {}
+
+
+def oracle_2000(variant):
+    """The oracle's state of a small-cavity variant after 2000 steps (computed once)."""
+    if variant not in _ORACLE_2000:
+        o = oracle_run(small_cavity(variant), 2000)
+        _ORACLE_2000[variant] = (o.fields(), o.stats())
+    return _ORACLE_2000[variant]
+
+
+# Launch paths of a single cavity: (pattern, steps per launch, segment rows).
+# "ab3" is the benchmark's kernel (two lattices, three steps per launch,
+# 4-row segments); "ab2" the two-step kernel; "ab1" single two-lattice steps.
+PATHS = {"aa": (0, 1, 0), "ab1": (1, 1, 0), "ab2": (1, 2, 2), "ab3": (1, 3, 4)}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("variant", ["literal", "eq6", "distinct"])
-def test_small_cavity_2000_steps(ctx, variant):
-    case = small_cavity(variant)
-    print(f"case small_cavity[{variant}] 128x64 FP64 2000 steps", flush=True)
-    s = ctx.add(case)
-    ctx.step(s, 2000)
-    got, st = ctx.fields(s), ctx.reduce(s)
-    o = oracle_run(case, 2000)
-    want, ost = o.fields(), o.stats()
+def test_small_cavity_2000_steps(P, variant, path):
+    """Eq. (2) end to end: 2000 steps from all solid on every launch path,
+    against the oracle at the FP64 bar."""
+    pattern, fuse, seg = PATHS[path]
+    case = dict(small_cavity(variant), pattern=pattern)
+    print(f"case small_cavity[{variant}] 128x64 FP64 2000 steps, path {path}", flush=True)
+    with P.Context(device=0, max_slots=1) as ctx:
+        if pattern == 1:
+            ctx.set_fusion(0, fuse, seg or None)
+        s = ctx.add(case)
+        if pattern == 1:
+            assert ctx.slot_fusion(s)[0] == fuse
+        ctx.step(s, 2000)
+        got, st = ctx.fields(s), ctx.reduce(s)
+    want, ost = oracle_2000(variant)
+    _check_small_cavity(got, st, want, ost)
+
+
+@pytest.mark.parametrize("fuse", [1, 2, 3])
+def test_small_cavity_2000_steps_batched(P, fuse):
+    """The three rate variants advance together in batched launches (two
+    lattices, `fuse` steps per launch, 100-step graphs) beside an in-place copy
+    of each; all six against the oracle at the FP64 bar."""
+    variants = ["literal", "eq6", "distinct"]
+    print(f"case small_cavity x3 batched, {fuse} steps per launch, 2000 steps", flush=True)
+    with P.Context(device=0, max_slots=6) as ctx:
+        ctx.set_fusion(0, fuse, 4 if fuse == 3 else None)
+        ctx.set_graph_chunk(100)
+        slots = [ctx.add(dict(small_cavity(v), pattern=pat)) for pat in (1, 0) for v in variants]
+        ctx.step_many(slots, [2000] * len(slots))
+        res = [(ctx.fields(s), ctx.reduce(s)) for s in slots]
+    for k, (got, st) in enumerate(res):
+        want, ost = oracle_2000(variants[k % 3])
+        _check_small_cavity(got, st, want, ost)
+
+
+def _check_small_cavity(got, st, want, ost):
     err = max_field_err(got, want)
     assert err["H"] <= TOL and err["ux"] <= TOL and err["uy"] <= TOL, err
     assert max(err.values()) <= TOL, err
@@ -242,6 +289,21 @@ def test_checkpoint_resume_is_bitwise(P, pattern, prec):
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
     for k in ("step", "melt_fraction", "total_H", "heat_in_cum", "budget_residual", "nusselt"):
         assert got_st[k] == want_st[k], k
+    # the resumed run against an uninterrupted oracle run of 1000 steps
+    o = oracle_run(case, 1000)
+    ost = o.stats()
+    if prec == 0:
+        with P.Context(device=0, max_slots=1) as ctx:
+            s = ctx.add(case)
+            ctx.state_load(s, *got)
+            fields = ctx.fields(s)
+        err = max_field_err(fields, o.fields())
+        assert max(err.values()) <= TOL, err
+        assert got_st["melt_fraction"] == pytest.approx(ost["melt_fraction"], abs=1e-12)
+        assert got_st["nusselt"] == pytest.approx(ost["nusselt"], rel=1e-10)
+    else:
+        assert abs(got_st["melt_fraction"] - ost["melt_fraction"]) <= 1e-4
+        assert abs(got_st["nusselt"] - ost["nusselt"]) <= 5e-3 * abs(ost["nusselt"])
 
 
 FUSED_GEOMS = GEOMS + [(130, 70, 0, 0, 0.4, 0.3), (200, 37, 1, 1, 0.5, 0.25), (63, 17, 1, 0, 0.6, 0.5)]

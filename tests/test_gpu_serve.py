@@ -1,10 +1,26 @@
 """Serving on the GPU: requests that arrive while others run are admitted as
 memory frees up, share batched launches, and each result equals the same
 solve run alone (bitwise, since the batched and single-cavity launches
-perform the same arithmetic).  A request that goes non-finite fails alone."""
+perform the same arithmetic) and the FP64 oracle's: FP64 requests at the FP64
+bar, FP32-shifted ones within 1e-4 in melt fraction and 0.5 % in Nusselt
+number.  A request that goes non-finite fails alone."""
+import numpy as np
 import pytest
 
+import oracle
 from btrirt_workloads import cavity
+
+_ORACLE = {}
+
+
+def oracle_result(case, steps):
+    """Fields and stats of the oracle after `steps` steps from all solid (the
+    oracle ignores precision and storage pattern, so runs are shared)."""
+    key = (tuple(sorted((k, v) for k, v in case.items() if k not in ("precision", "pattern"))), steps)
+    if key not in _ORACLE:
+        o = oracle.Oracle(oracle.case_from_dict(case)).init_solid().step(steps)
+        _ORACLE[key] = (o.fields(), o.stats())
+    return _ORACLE[key]
 
 pytestmark = pytest.mark.gpu
 
@@ -15,11 +31,12 @@ def P():
     return P
 
 
-def solo_stats(P, case, steps):
+def solo_stats(P, case, steps, fields=False):
     with P.Context(device=0, max_slots=1) as ctx:
         s = ctx.add(case)
         ctx.step(s, steps)
-        return ctx.reduce(s, allow_unstable=True)
+        st = ctx.reduce(s, allow_unstable=True)
+        return (st, ctx.fields(s)) if fields else st
 
 
 def _trace(P, patterns):
@@ -58,11 +75,23 @@ def test_served_results_equal_solo_runs(P, patterns):
     assert summ["max_resident"] >= 2
     for r, (c, steps, _) in zip(recs, trace):
         assert r["status"] == serve.LBM_REQ_DONE
-        want = solo_stats(P, c, steps)
+        want, fields = solo_stats(P, c, steps, fields=True)
         got = r["stats"]
         assert got["step"] == steps
         for k in ("melt_fraction", "total_H", "heat_in_cum", "nusselt", "mass", "max_u", "budget_residual"):
             assert got[k] == want[k], (r["id"], k)
+        # the request in the mix against the oracle
+        ofields, ost = oracle_result(c, steps)
+        if c["precision"] == P.LBM_FP64:
+            err = {n: float(np.max(np.abs(fields[n] - ofields[n]))) for n in ("H", "ux", "uy", "T", "fl")}
+            assert max(err.values()) <= 1e-10, (r["id"], err)
+            assert got["melt_fraction"] == pytest.approx(ost["melt_fraction"], abs=1e-12), r["id"]
+            assert got["nusselt"] == pytest.approx(ost["nusselt"], rel=1e-10), r["id"]
+            assert got["total_H"] == pytest.approx(ost["total_H"], rel=1e-12), r["id"]
+            assert got["heat_in_cum"] == pytest.approx(ost["heat_in_cum"], rel=1e-12), r["id"]
+        else:
+            assert abs(got["melt_fraction"] - ost["melt_fraction"]) <= 1e-4, r["id"]
+            assert abs(got["nusselt"] - ost["nusselt"]) <= 5e-3 * abs(ost["nusselt"]), r["id"]
 
 
 def test_unstable_request_fails_alone(P):

@@ -1,7 +1,10 @@
 """Melt-fraction and Nusselt time series of the large cavity's physics on a
 256x128 downscale (Ra 1e8, Pr 1, Ste 1, heater W/4 centred), 20000 steps from
 all solid, recorded every 100 steps on the device and compared with the FP64
-oracle at the same steps; the FP32-shifted path is compared with it too."""
+oracle at the same steps, in place and on the benchmark's kernel (two
+lattices, three steps per launch, 4-row segments; a report every 100 steps
+makes each 100-step stretch 32 three-step launches and two two-step ones);
+the FP32-shifted path is compared with it too."""
 import numpy as np
 import pytest
 
@@ -29,18 +32,23 @@ def oracle_series():
     return out
 
 
-def gpu_series(P, precision):
-    case = dict(large_cavity(256, 128), precision=precision)
+def gpu_series(P, precision, pattern=0):
+    case = dict(large_cavity(256, 128), precision=precision, pattern=pattern)
     with P.Context(device=0, max_slots=1) as ctx:
+        if pattern == 1:
+            ctx.set_fusion(precision, 3, 4)
         s = ctx.add(case)
+        if pattern == 1:
+            assert ctx.slot_fusion(s) == (3, 4)
         ctx.set_report(s, EVERY, STEPS // EVERY)
         ctx.step(s, STEPS)
         return ctx.series(s)
 
 
-def test_fp64_series_matches_oracle(P, oracle_series):
-    print("case 256x128 Ra 1e8 FP64, 20000 steps, series every 100", flush=True)
-    ser = gpu_series(P, P.LBM_FP64)
+@pytest.mark.parametrize("pattern", [0, 1], ids=["in_place", "three_step"])
+def test_fp64_series_matches_oracle(P, oracle_series, pattern):
+    print(f"case 256x128 Ra 1e8 FP64 pattern {pattern}, 20000 steps, series every 100", flush=True)
+    ser = gpu_series(P, P.LBM_FP64, pattern)
     assert [e["step"] for e in ser] == [EVERY * (k + 1) for k in range(STEPS // EVERY)]
     dphi = max(abs(a["melt_fraction"] - b["melt_fraction"]) for a, b in zip(ser, oracle_series))
     dnu = max(abs(a["nusselt"] - b["nusselt"]) / abs(b["nusselt"]) for a, b in zip(ser, oracle_series))
@@ -53,9 +61,10 @@ def test_fp64_series_matches_oracle(P, oracle_series):
     assert all(e["finite"] == 1 for e in ser)
 
 
-def test_fp32_series_tracks_fp64(P, oracle_series):
-    print("case 256x128 Ra 1e8 FP32 shifted, 20000 steps, series every 100", flush=True)
-    ser = gpu_series(P, P.LBM_FP32_SHIFTED)
+@pytest.mark.parametrize("pattern", [0, 1], ids=["in_place", "three_step"])
+def test_fp32_series_tracks_fp64(P, oracle_series, pattern):
+    print(f"case 256x128 Ra 1e8 FP32 shifted pattern {pattern}, 20000 steps, series every 100", flush=True)
+    ser = gpu_series(P, P.LBM_FP32_SHIFTED, pattern)
     dphi = np.array([abs(a["melt_fraction"] - b["melt_fraction"]) for a, b in zip(ser, oracle_series)])
     dnu = np.array([abs(a["nusselt"] - b["nusselt"]) / abs(b["nusselt"]) for a, b in zip(ser, oracle_series)])
     print(f"  max|dphi|={dphi.max():.2e} max|dNu|/Nu={dnu.max():.2e}", flush=True)

@@ -57,6 +57,16 @@ MUTANTS = [
      "ns = 1.0 - fl;", "ns = fl;"),
     ("partial bounce-back of the post-collision populations",
      "ns * f[OPP[i]]", "ns * fout[OPP[i]]"),
+    ("max |u| from the vertical component only",
+     "double u = sqrt(m[3] * m[3] + m[4] * m[4]);", "double u = fabs(m[4]);"),
+    ("max |u| as the sum of the component magnitudes",
+     "double u = sqrt(m[3] * m[3] + m[4] * m[4]);", "double u = fabs(m[3]) + fabs(m[4]);"),
+    ("Fourier number over the cavity area",
+     "out->fourier = p->alpha * (double)st->step / ((double)p->ny * (double)p->ny);",
+     "out->fourier = p->alpha * (double)st->step / ((double)p->nx * (double)p->ny);"),
+    ("Fourier number without the square of the height",
+     "out->fourier = p->alpha * (double)st->step / ((double)p->ny * (double)p->ny);",
+     "out->fourier = p->alpha * (double)st->step / (double)p->ny;"),
 ]
 
 PIN_CHECKS = [
@@ -76,6 +86,7 @@ PIN_CHECKS = [
     pins.test_gaussian_variance_grows_at_twice_alpha_1d,
     pins.test_walled_cavity_budget_closes,
     pins.test_centred_heater_is_mirror_symmetric,
+    lambda: pins.test_max_velocity_of_a_moving_cell((0.03, -0.04)),
     lambda: solid.test_darcy_velocity_is_the_mean_momentum_and_momentum_gains_the_total_force(0),
     lambda: solid.test_partial_bounce_back_mixes_free_fluid_and_full_bounce_back(0),
     lambda: solid.test_liquid_cell_is_a_free_fluid_under_every_reading(oracle.SOLID_DARCY),

@@ -253,6 +253,10 @@ def test_stefan_interface_temperature_and_nusselt():
     assert np.all(T[y > Xi + 1.0] == 0.0)
     nu_an = ny / (math.sqrt(math.pi * alpha * steps) * math.erf(kappa))
     assert o.stats()["nusselt"] == pytest.approx(nu_an, rel=0.03)
+    # the Fourier number the oracle reports places the front where Eq. (7)
+    # puts it in units of the column height: X_i / ny = 2 kappa sqrt(Fo)
+    fo = o.stats()["fourier"]
+    assert fl.sum() / ny == pytest.approx(2 * kappa * math.sqrt(fo), rel=0.02)
 
 
 def test_stefan_interface_converges_with_time():
@@ -480,3 +484,34 @@ def test_solid_cells_never_move():
         solid = fld["fl"] == 0.0
         assert solid.sum() > 0
         assert np.all(fld["ux"][solid] == 0.0) and np.all(fld["uy"][solid] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# max |u| of the reported diagnostics: a closed form
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("u", [(0.03, -0.04), (-0.05, 0.0), (0.0, 0.05), (0.028, 0.096)])
+def test_max_velocity_of_a_moving_cell(u):
+    """One liquid cell at T = Tm (so no buoyancy) holds the second-order
+    equilibrium of velocity u, every other cell is at rest: the first moment
+    of that equilibrium is rho0 u exactly, so the reported max |u| is the
+    Euclidean norm of u (0.05 or 0.1 here), whichever component carries it."""
+    nx, ny, rho0, Tm, latent = 6, 5, 1.0, 0.1, 1.0
+    case = lattice_case(nx, ny, periodic_x=1, periodic_y=1, Tm=Tm, Th=1.0, latent=latent, rho0=rho0)
+    o = oracle.Oracle(case)
+    cx, cy, w = oracle.CX, oracle.CY, oracle.W
+    H = Tm + latent  # fully liquid at Tm: fl = 1, T = Tm
+    f = np.broadcast_to((w * rho0)[:, None, None], (9, ny, nx)).copy()
+    g = np.broadcast_to((w * H)[:, None, None], (9, ny, nx)).copy()
+    g[0] = H - Tm + w[0] * Tm  # the latent part sits in the rest population, Eq. (3)
+    g[1:] = (w[1:] * Tm)[:, None, None]
+    cu = cx * u[0] + cy * u[1]
+    uu = u[0] ** 2 + u[1] ** 2
+    f[:, 2, 3] = w * (rho0 + rho0 * (3 * cu + 4.5 * cu ** 2 - 1.5 * uu))
+    g[:, 2, 3] = w * Tm * (1 + 3 * cu)
+    g[0, 2, 3] = H - Tm + w[0] * Tm
+    o.set_populations(f, g)
+    st = o.stats()
+    assert st["max_u"] == pytest.approx(math.hypot(*u), rel=1e-12)
+    fld = o.fields()
+    assert fld["ux"][2, 3] == pytest.approx(u[0], abs=1e-15)
+    assert fld["uy"][2, 3] == pytest.approx(u[1], abs=1e-15)
