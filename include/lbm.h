@@ -210,6 +210,20 @@ int lbm_reduce(lbm_ctx *c, int slot, lbm_stats *out);
  * LBM_ENOMEM when the device staging buffer cannot grow.  Blocks. */
 int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_fields
+ * with its device staging in a fixed array of 16 MiB (2^24 bytes) of static
+ * device memory instead of a buffer the context grows with hipMalloc.  Each
+ * GPU the library runs on holds its own copy of that array from the first
+ * context on it until the process ends; the call itself allocates nothing.
+ * Same arguments, layout and results as lbm_fields (bit for bit).
+ * LBM_EINVAL when the requested planes need more than 16 MiB (8 bytes per
+ * cell and field: one field of 2048x1024 cells, or all six of 512x512).
+ * Every call on one GPU, from any context or thread of the process, shares
+ * the array: calls that overlap in time on one GPU race and must be
+ * serialised by the caller.  Blocks. */
+int lbm_fields_noalloc(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n);
+
 /* Records diagnostics every `every` steps into a device ring of `capacity`
  * entries while lbm_step runs (every = 0 stops).  Clears earlier entries. */
 int lbm_set_report(lbm_ctx *c, int slot, int64_t every, int32_t capacity);

@@ -37,7 +37,7 @@ EXPORTS = (
     "lbm_checkpoint_bytes", "lbm_checkpoint_save", "lbm_checkpoint_load", "lbm_checkpoint_info",
     "lbm_set_fusion", "lbm_get_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
-    "lbm_server_request", "lbm_server_summary", "lbm_server_on_finish",
+    "lbm_server_request", "lbm_server_summary", "lbm_server_on_finish", "lbm_fields_noalloc",
 )
 
 
@@ -154,6 +154,7 @@ def lib():
             "lbm_set_group_bytes": (ctypes.c_int, [vp, ctypes.c_size_t]),
             "lbm_reduce": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_stats)]),
             "lbm_fields": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_uint32, _dp, ctypes.c_size_t]),
+            "lbm_fields_noalloc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_uint32, _dp, ctypes.c_size_t]),
             "lbm_set_report": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int32]),
             "lbm_series": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_stats), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]),
@@ -272,6 +273,15 @@ def lbm_fields(ctx, slot, nx, ny, mask=63):
     names = [n for b, n in enumerate(FIELD_NAMES) if mask & (1 << b)]
     buf = np.empty((len(names), ny, nx), dtype=np.float64)
     _check(lib().lbm_fields(ctx, int(slot), int(mask), _ptr(buf), buf.size))
+    return {n: buf[k] for k, n in enumerate(names)}
+
+
+def lbm_fields_noalloc(ctx, slot, nx, ny, mask=63):
+    """lbm_fields through the library's fixed device staging array (no
+    device allocation)."""
+    names = [n for b, n in enumerate(FIELD_NAMES) if mask & (1 << b)]
+    buf = np.empty((len(names), ny, nx), dtype=np.float64)
+    _check(lib().lbm_fields_noalloc(ctx, int(slot), int(mask), _ptr(buf), buf.size))
     return {n: buf[k] for k, n in enumerate(names)}
 
 

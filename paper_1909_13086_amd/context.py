@@ -79,6 +79,10 @@ class Context:
         nx, ny = self._shape[slot]
         return L.lbm_fields(self.h, slot, nx, ny, mask)
 
+    def fields_noalloc(self, slot, mask=63):
+        nx, ny = self._shape[slot]
+        return L.lbm_fields_noalloc(self.h, slot, nx, ny, mask)
+
     def state_load(self, slot, f, g):
         L.lbm_state_load(self.h, slot, f, g)
 

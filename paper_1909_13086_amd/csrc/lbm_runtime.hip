@@ -43,6 +43,14 @@ int fail(int code, const std::string &msg) {
       return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
   } while (0)
 
+// Device staging of lbm_fields_noalloc: fixed file-scope device memory, one
+// copy on every GPU the library runs on, held until the process ends.  Host
+// code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (lbm_create keeps it in the context); the array's name in
+// host code is not a device address.
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
 constexpr double kCs2 = 1.0 / 3.0;
 constexpr int kPitchAlign = 64;  // cells: one wavefront per row segment
 constexpr size_t kByteAlign = 256;
@@ -277,6 +285,7 @@ struct lbm_ctx {
   StatsDev *stats_host = nullptr;  // pinned, 2 entries: current state and state at load
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  void *noalloc = nullptr;         // this device's copy of noalloc_scratch (kNoAllocBytes)
   LaunchCfg launch[2] = {lbm::default_launch(0), lbm::default_launch(1)};
   int graph_chunk = 0;
   int num_cus = 256;
@@ -983,6 +992,14 @@ int lbm_create(lbm_ctx **out, int device, void *hip_stream, size_t hbm_budget, i
        hipHostMalloc(&c->stats_host, 2 * sizeof(StatsDev)) != hipSuccess))
     rc = fail(LBM_ENOMEM, "cannot allocate reduction scratch");
   if (rc == LBM_OK) {
+    // the device is current: its copy of the static staging array
+    const hipError_t e = hipGetSymbolAddress(&c->noalloc, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !c->noalloc) {
+      c->noalloc = nullptr;
+      rc = fail(LBM_EDEVICE, std::string("cannot resolve the static staging array: ") + hipGetErrorString(e));
+    }
+  }
+  if (rc == LBM_OK) {
     *c->err_host = 0;
     if (lbm::launch_fill_zero(c->err_dev, sizeof(int32_t), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
@@ -1158,6 +1175,29 @@ int lbm_fields(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n) {
                              c->stream));
   HIP_TRY(hipMemcpyAsync(host, c->scratch, planes * cells * sizeof(double),
                          hipMemcpyDeviceToHost, c->stream));
+  return sync_checked(c);
+}
+
+int lbm_fields_noalloc(lbm_ctx *c, int slot, uint32_t mask, double *host, size_t n) {
+  TraceRange range("lbm_fields_noalloc");
+  int rc = check_slot(c, slot);
+  if (rc != LBM_OK) return rc;
+  Slot &s = c->slots[slot];
+  mask &= 63u;
+  int planes = 0;
+  for (int b = 0; b < 6; ++b) planes += (mask >> b) & 1u;
+  const size_t cells = (size_t)s.cs.nx * s.cs.ny;
+  if (!host || planes == 0 || n < planes * cells)
+    return fail(LBM_EINVAL, "host buffer too small or empty mask");
+  const size_t bytes = planes * cells * sizeof(double);
+  if (bytes > kNoAllocBytes)
+    return fail(LBM_EINVAL, "lbm_fields_noalloc: " + std::to_string(planes) + " field(s) of " +
+                                std::to_string(cells) + " cells need " + std::to_string(bytes) +
+                                " bytes of staging, above the fixed " + std::to_string(kNoAllocBytes) +
+                                " bytes; ask for fewer fields or use lbm_fields");
+  if (!c->noalloc) return fail(LBM_ESTATE, "static staging array not resolved for this device");
+  HIP_TRY(lbm::launch_fields(s.dev, s.cs.precision, mask, static_cast<double *>(c->noalloc), c->stream));
+  HIP_TRY(hipMemcpyAsync(host, c->noalloc, bytes, hipMemcpyDeviceToHost, c->stream));
   return sync_checked(c);
 }
 
