@@ -190,8 +190,12 @@ def fp32_variant(P, steps, path="ab"):
     pattern = (f"two lattices, {fuse} steps per launch, rows staged through LDS, {seg}-row segments"
                if path != "aa" else PATHS[path]["pattern"])
     log(f"fp32s ({pattern}): {mlups:.0f} MLUPS")
-    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=pattern,
-                hbm_frac=round(mlups * 1e6 * BYTES_PER_LU[1] / (HBM_PEAK_GBS * 1e9), 4),
+    per = fuse if path != "aa" else 1
+    # bytes a launch must move (144 B per cell) over the time of one launch
+    gbs = BYTES_PER_LU[1] * cells / (ms / steps * per * 1e-3) / 1e9
+    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=pattern, steps_per_launch=per,
+                achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                effective_gbs=round(BYTES_PER_LU[1] * cells * steps / (ms * 1e-3) / 1e9, 1),
                 melt_fraction=st["melt_fraction"])
 
 
@@ -212,10 +216,12 @@ def hbm_bound_variant(P, steps=240):
             ctx.close()
             cells = 4096 * 2048
             us = ms * 1e3 / steps
-            gbs = BYTES_PER_LU[prec] * cells / (us * 1e-6) / 1e9
+            # bytes a launch must move over the time of one launch (fuse steps)
+            gbs = BYTES_PER_LU[prec] * cells / (us * fuse * 1e-6) / 1e9
             out[f"{pname}_{name}"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
                                           steps_per_launch=fuse, achieved_gbs=round(gbs, 1),
-                                          frac=round(gbs / HBM_PEAK_GBS, 4))
+                                          frac=round(gbs / HBM_PEAK_GBS, 4),
+                                          effective_gbs=round(BYTES_PER_LU[prec] * cells / (us * 1e-6) / 1e9, 1))
     log(f"hbm-bound 4096x2048: {out}")
     return out
 
@@ -237,10 +243,11 @@ def fused_sizes_variant(P, steps=480):
             ctx.close()
             us = ms * 1e3 / steps
             cells = nx * ny
-            gbs = BYTES_PER_LU[0] * cells / (us * 1e-6) / 1e9
+            gbs = BYTES_PER_LU[0] * cells / (us * fuse * 1e-6) / 1e9
             out[f"{nx}x{ny}_{fuse}step"] = dict(us_per_step=round(us, 2), mlups=round(cells / us, 1),
                                                 us_per_launch=round(fuse * us, 2),
-                                                achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+                                                achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                                                effective_gbs=round(BYTES_PER_LU[0] * cells / (us * 1e-6) / 1e9, 1))
     log(f"fused two-lattice FP64: {out}")
     return out
 

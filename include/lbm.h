@@ -287,8 +287,8 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * that are not a multiple end with shorter launches.  Batched launches
  * (lbm_step_many) fuse as many steps as the slot's single-cavity launches.
  * Results equal those of single steps bit for bit.  Default: 3 steps per
- * launch in segments of 4 rows (FP64) or 6 rows (FP32); two-step segments
- * of 2 rows (FP64) or 4 rows (FP32).  Until lbm_set_fusion or lbm_autotune
+ * launch in segments of 6 rows; two-step segments of 2 rows (FP64) or 4
+ * rows (FP32).  Until lbm_set_fusion or lbm_autotune
  * sets it, the default follows each cavity's size: FP64 cavities below 2^20
  * cells take two steps per launch, three-step segments shrink to 4, 2 or 1
  * rows until a launch has at least 1024 wavefronts (lbm_slot_fusion shows

@@ -64,14 +64,14 @@ constexpr int kStripCols = kWave - 2;   // owned columns of a two-step wavefront
 constexpr int kStrip3Cols = kWave - 4;  // owned columns of a three-step wavefront
 
 // Defaults per precision, the fastest measured on MI355X at 2048x1024 and
-// 4096x2048: three steps per launch in segments of 4 rows (FP64) or 6 rows
-// (FP32); two-step launches (the batched path, shorter remainders) in
-// segments of 2 rows (FP64) or 4 rows (FP32).
+// 4096x2048: three steps per launch in segments of 6 rows; two-step launches
+// (the batched path, shorter remainders) in segments of 2 rows (FP64) or 4
+// rows (FP32).
 inline LaunchCfg default_launch(int precision) {
   LaunchCfg L;
   L.fuse = 3;
   L.seg = precision == 0 ? 2 : 4;
-  L.seg3 = precision == 0 ? 4 : 6;
+  L.seg3 = 6;
   return L;
 }
 

@@ -35,6 +35,10 @@ using namespace dev;
 
 constexpr int kDirectWaves = 4;        // wavefronts per workgroup, direct rows
 constexpr int kStagedWaves = 2;        // wavefronts per workgroup, staged rows
+// wavefronts per workgroup of the single-cavity three-step launch: one, so a
+// CU starts a new segment as soon as any wavefront finishes (its 18 KiB of LDS
+// are its own)
+constexpr int kStep3Waves = 1;
 
 // The three populations that move along the walk direction D (c_y = D):
 // 2, 5, 6 going up, 4, 7, 8 going down -> window slots 0, 1, 2.
@@ -583,7 +587,7 @@ __device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, 
 // slot when the third step gathers.  Each lane reads and writes only its own
 // column of a slot, and LDS operations of a wavefront complete in order, so
 // no barrier is needed.
-template <typename S, typename R, int D, bool WALLS, int MODEL, int STEPS = 3>
+template <typename S, typename R, int D, bool WALLS, int MODEL, int STEPS = 3, bool PIPE = true>
 __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
                                            S *__restrict__ B, const Col &q, int y0, int y1, R *ring) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -610,13 +614,26 @@ __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, co
     af[0] = p[a0 * kWave]; af[1] = p[a1 * kWave]; af[2] = p[a2 * kWave];
     ag[0] = p[(kQ + a0) * kWave]; ag[1] = p[(kQ + a1) * kWave]; ag[2] = p[(kQ + a2) * kWave];
   };
-  auto level1 = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
-    if (!(row_real<2>(c, r) && q.real)) {
+  // level 1 in two halves: the loads of a row, and its collision once they are
+  // in.  The loads sit outside every branch, so the wavefront need not wait
+  // for them where they are issued: a lane whose column does not exist loads
+  // column 0 of the row, and a row that does not exist loads the nearest row
+  // of the cavity; such values are never used (the links that would read them
+  // are reflected at the wall), and rows that do not exist are zeroed.
+  const int lcol = q.real ? q.xw : 0;
+  auto load1 = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
+    const int rr = row_real<2>(c, r) ? row_wrap<2>(c, r) : min(max(r, 0), c.ny - 1);
+    load_natural<S, R>(A, c.plane, cell_base(c, lcol, rr), f, g);
+  };
+  auto collide1 = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
+    if (row_real<2>(c, r))  // wavefront-uniform
+      first_collide<R, MODEL>(c, k, q, r, f, g);
+    else
       zero_row(f, g);
-      return;
-    }
-    load_natural<S, R>(A, c.plane, cell_base(c, q.xw, row_wrap<2>(c, r)), f, g);
-    first_collide<R, MODEL>(c, k, q, r, f, g);
+  };
+  auto level1 = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
+    load1(r, f, g);
+    collide1(r, f, g);
   };
   auto level2 = [&](int r, const R (&cf)[kQ], const R (&cg)[kQ], const R (&nf)[kQ],
                     const R (&ng)[kQ], const R (&af)[3], const R (&ag)[3], R (&f)[kQ], R (&g)[kQ]) {
@@ -641,9 +658,16 @@ __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, co
     put(ys, t2f, t2g);
     slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
   }
-  for (int y = ys; y != ye; y += D) {
+  // PIPE: the loads of each walk row are issued one iteration early, before
+  // the third step and the stores of the previous row, so they overlap that
+  // work instead of being waited for right after their issue; the last
+  // iteration, which has no next row, is peeled off so that the loop always
+  // loads.  This holds one row more in registers (the batched kernel, whose
+  // item loop needs more of them, loads each row when it collides it).
+  auto iteration = [&](int y, auto load_next) {
     R n2f[kQ], n2g[kQ];
-    level1(y + 2 * D, n1f, n1g);
+    if constexpr (!PIPE) load1(y + 2 * D, n1f, n1g);
+    collide1(y + 2 * D, n1f, n1g);
     level2(y + D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
     slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
     if constexpr (STEPS == 3) {
@@ -652,19 +676,24 @@ __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, co
       put(y + D, n2f, n2g);  // the slot of row y-D
       R c2f[kQ], c2g[kQ], pf[kQ], pg[kQ];
       get(y, c2f, c2g);
+      if constexpr (PIPE && decltype(load_next)::value) load1(y + 3 * D, n1f, n1g);
       second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
       emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
     } else {
       R c2f[kQ], c2g[kQ];
       get(y, c2f, c2g);
       put(y + D, n2f, n2g);
+      if constexpr (PIPE && decltype(load_next)::value) load1(y + 3 * D, n1f, n1g);
       emit<S, R, WALLS, false>(c, k, B, q, y, c2f, c2g);
     }
-  }
+  };
+  if constexpr (PIPE) load1(ys + 2 * D, n1f, n1g);
+  for (int y = ys; y != ye - D; y += D) iteration(y, std::true_type{});
+  iteration(ye - D, std::false_type{});
 }
 
 // The three-step walk for either precision, direction and wall case.
-template <typename S, typename R, int MODEL, int STEPS>
+template <typename S, typename R, int MODEL, int STEPS, bool PIPE = false>
 __device__ __forceinline__ void walk3(bool down, bool inner, const CavDev &c, const Coef<R> &k,
                                       const S *__restrict__ A, S *__restrict__ B, const Col &q, int y0,
                                       int y1, int x0, R *mine) {
@@ -672,14 +701,14 @@ __device__ __forceinline__ void walk3(bool down, bool inner, const CavDev &c, co
     // FP64: level-2 ring of two rows of R
     if (down) {
       if (inner)
-        walk3_ring<S, R, -1, false, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+        walk3_ring<S, R, -1, false, MODEL, STEPS, PIPE>(c, k, A, B, q, y0, y1, mine);
       else
-        walk3_ring<S, R, -1, true, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+        walk3_ring<S, R, -1, true, MODEL, STEPS, PIPE>(c, k, A, B, q, y0, y1, mine);
     } else {
       if (inner)
-        walk3_ring<S, R, +1, false, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+        walk3_ring<S, R, +1, false, MODEL, STEPS, PIPE>(c, k, A, B, q, y0, y1, mine);
       else
-        walk3_ring<S, R, +1, true, MODEL, STEPS>(c, k, A, B, q, y0, y1, mine);
+        walk3_ring<S, R, +1, true, MODEL, STEPS, PIPE>(c, k, A, B, q, y0, y1, mine);
     }
   } else {
     // FP32: two staged rows of S
@@ -699,14 +728,14 @@ __device__ __forceinline__ void walk3(bool down, bool inner, const CavDev &c, co
 }
 
 template <typename S, typename R, int MODEL>
-__global__ __launch_bounds__(kStagedWaves * kWave)
+__global__ __launch_bounds__(kStep3Waves * kWave)
 __attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int nseg, int seg_rows,
                                                      int order) {
-  __shared__ R lds[kStagedWaves * 2 * kPlanes * kWave];
+  __shared__ R lds[kStep3Waves * 2 * kPlanes * kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int b = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
-  const int w = b * kStagedWaves + wid;
+  const int w = b * kStep3Waves + wid;
   if (w >= strips_x * nseg) return;  // uniform per wavefront; no barriers follow
   const int strip = w % strips_x, seg = w / strips_x;
   const int x0 = strip * kStrip3Cols;
@@ -718,7 +747,7 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step3(CavDev c, int strips_x, int
   S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
   const bool down = (order & 4) && (seg & 1);
   R *mine = lds + wid * 2 * kPlanes * kWave;
-  walk3<S, R, MODEL, 3>(down, interior_segment<2>(c, x0, y0, y1), c, k, A, B, q, y0, y1, x0, mine);
+  walk3<S, R, MODEL, 3, true>(down, interior_segment<2>(c, x0, y0, y1), c, k, A, B, q, y0, y1, x0, mine);
 }
 
 template <typename S, typename R>
@@ -727,10 +756,10 @@ hipError_t dispatch3(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int strips_x = (c.nx + kStrip3Cols - 1) / kStrip3Cols;
   const int nseg = (c.ny + cfg.seg3 - 1) / cfg.seg3;
   const int waves = strips_x * nseg;
-  const dim3 grid((waves + kStagedWaves - 1) / kStagedWaves);
+  const dim3 grid((waves + kStep3Waves - 1) / kStep3Waves);
   const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
   with_model(c.solid_model, [&](auto m) {
-    hipLaunchKernelGGL((k_step3<S, R, decltype(m)::value>), grid, dim3(kStagedWaves * kWave), 0, s, c,
+    hipLaunchKernelGGL((k_step3<S, R, decltype(m)::value>), grid, dim3(kStep3Waves * kWave), 0, s, c,
                        strips_x, nseg, cfg.seg3, order);
     return 0;
   });

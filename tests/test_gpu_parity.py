@@ -362,7 +362,7 @@ def test_fused_kernels_in_graphs_and_with_reports(P, chunk):
 
 def test_fused_kernels_full_size_match_oracle(P):
     """The benchmark's FP64 workload in its launch configuration (three steps
-    per launch, 4-row segments) and with two steps per launch, 6 steps from a
+    per launch, 6-row segments) and with two steps per launch, 6 steps from a
     random state, against the oracle."""
     case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB)
     print("case 2048x1024 FP64 fused kernels, 6 steps vs oracle", flush=True)
@@ -371,7 +371,7 @@ def test_fused_kernels_full_size_match_oracle(P):
     for fuse in (3, 2):
         with P.Context(device=0, max_slots=1) as ctx:  # default launch configuration
             if fuse == 3:
-                assert ctx.get_fusion(0) == (3, 4)
+                assert ctx.get_fusion(0) == (3, 6)
                 assert ctx.get_launch(0)[3] == P.LBM_LAUNCH_DEFAULT
             else:
                 ctx.set_fusion(0, 2)
@@ -392,7 +392,7 @@ def test_default_fusion_follows_cavity_size(P):
     1024 wavefronts); an explicit setting is used as given.  The adapted
     launches equal single steps bit for bit."""
     print("case default fusion per cavity size", flush=True)
-    cases = [((2048, 1024, 0), (3, 4)), ((1024, 512, 0), (2, 2)), ((2048, 1024, 1), (3, 6)),
+    cases = [((2048, 1024, 0), (3, 6)), ((1024, 512, 0), (2, 2)), ((2048, 1024, 1), (3, 6)),
              ((1024, 512, 1), (3, 6)), ((768, 384, 1), (3, 4)), ((512, 256, 1), (3, 2)),
              ((128, 64, 1), (3, 1))]
     with P.Context(device=0, max_slots=len(cases) + 1) as ctx:
