@@ -38,13 +38,14 @@ REPORT_EVERY = 100
 # traffic), counter summary, steps per launch
 CSRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc")
 PATHS = {
-    "ab": dict(kernel="k_step3<double,double,0>", src=("lbm_device.h", "lbm_step2.hip"),
+    "ab": dict(kernel="k_step3<double,double,0>", src=("lbm_internal.h", "lbm_device.h", "lbm_step2.hip"),
                traffic=os.path.join(ROOT, "profiles", "traffic_k_step3_fp64_2048x1024.md"), per_launch=3,
                pattern="two lattices, three steps per launch, level-2 window in LDS"),
-    "ab2": dict(kernel="k_step2<double,double,true,0>", src=("lbm_device.h", "lbm_step2.hip"),
+    "ab2": dict(kernel="k_step2<double,double,true,0>", src=("lbm_internal.h", "lbm_device.h", "lbm_step2.hip"),
                 traffic=os.path.join(ROOT, "profiles", "traffic_k_step2_fp64_2048x1024.md"), per_launch=2,
                 pattern="two lattices, two steps per launch, rows staged through LDS"),
-    "aa": dict(kernel="k_step<double,double,1,false,0>", src=("lbm_device.h", "lbm_step.hip"),
+    "aa": dict(kernel="k_step<double,double,1,false,0,SM> (SM = 0, 1: even and odd A-A steps)",
+               src=("lbm_internal.h", "lbm_device.h", "lbm_step.hip"),
                traffic=os.path.join(ROOT, "profiles", "traffic_k_step_fp64_2048x1024.md"), per_launch=1,
                pattern="in-place A-A, one step per launch"),
 }
@@ -161,6 +162,25 @@ def roofline(path, m):
             "kernel": PATHS[path]["kernel"], "kernel_avg_us": round(m["launch_ms"] * 1e3, 2),
             "steps_per_launch": m["steps_per_launch"], "algorithmic_bytes_per_launch": alg,
             "effective_gbs": round(BYTES_PER_LU[0] * m["cells"] * m["steps_per_launch"] / sec / 1e9, 1)}
+
+
+def stream_ceiling(P, lattice_bytes, launches=40):
+    """The layout's streaming ceiling at this lattice size, measured live with
+    the library's probe (lbm_stream_probe: every 64-cell chunk read once and
+    written once per launch, no arithmetic, in the step kernels' order): the
+    two-lattice pattern (read one lattice, write the other) and in place.
+    Each moves 2 x lattice_bytes per launch."""
+    ctx = P.Context(device=0, max_slots=1)
+    try:
+        ab = ctx.stream_probe(lattice_bytes, P.LBM_PATTERN_AB, launches)
+        aa = ctx.stream_probe(lattice_bytes, P.LBM_PATTERN_AA, launches)
+    finally:
+        ctx.close()
+    moved = 2 * lattice_bytes
+    res = {"lattice_bytes": lattice_bytes, "two_lattice_us": round(ab, 2), "in_place_us": round(aa, 2),
+           "two_lattice_gbs": round(moved / (ab * 1e-6) / 1e9, 1), "in_place_gbs": round(moved / (aa * 1e-6) / 1e9, 1)}
+    log(f"stream ceiling: {res}")
+    return res
 
 
 def in_place_variant(P, steps):
@@ -594,6 +614,12 @@ def main():
         "nusselt": m["stats"]["nusselt"],
         "budget_residual": m["stats"]["budget_residual"],
     }
+    # the fused launch against what a pure stream of its pattern achieves on this device
+    lattice_bytes = 18 * 8 * m["case"]["nx"] * m["case"]["ny"]
+    ceil = stream_ceiling(P, lattice_bytes)
+    pattern_us = ceil["in_place_us"] if path == "aa" else ceil["two_lattice_us"]
+    out["roofline"]["stream_ceiling"] = ceil
+    out["roofline"]["frac_of_stream_ceiling"] = round(pattern_us / (m["launch_ms"] * 1e3), 4)
     if not args.no_extras:
         if path != "aa":
             out["in_place_aa"] = in_place_variant(P, max(1000, args.steps // 4))

@@ -311,6 +311,20 @@ int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
  * of the two-step kernel, the same of the three-step kernel) and a cached
  * entry is reused. */
 int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path);
+/* Measurement aid: the streaming ceiling of the lattice layout, against which
+ * the step kernels' memory rate is read (no lattice arithmetic).  Allocates
+ * one buffer of `bytes` (in place, LBM_PATTERN_AA) or two (LBM_PATTERN_AB),
+ * rounded down to whole 64-cell chunks of 18 FP64 planes, and times
+ * `launches` launches (1 .. 100000) on the context stream after two untimed
+ * ones: each wavefront reads one chunk and writes it back in place or to the
+ * other buffer, in the order the step kernels use (XCD bands, direction and,
+ * for two buffers, source and destination alternating between launches).
+ * *us gets the mean time per launch in microseconds; the bytes moved per
+ * launch are twice the buffer size.  Buffers are freed before return.
+ * LBM_EINVAL for NULL arguments, a bad pattern or count, or fewer bytes than
+ * one chunk; LBM_ENOMEM if the buffers do not fit; LBM_EDEVICE on a HIP
+ * error.  Waits for the context stream before and after. */
+int lbm_stream_probe(lbm_ctx *c, size_t bytes, int pattern, int launches, double *us);
 /* Waits for all work on the context stream. */
 int lbm_sync(lbm_ctx *c);
 /* The hipStream_t the context orders its work on. */

@@ -38,6 +38,7 @@ EXPORTS = (
     "lbm_set_fusion", "lbm_get_fusion",
     "lbm_server_create", "lbm_server_destroy", "lbm_server_submit", "lbm_server_run",
     "lbm_server_request", "lbm_server_summary", "lbm_server_on_finish", "lbm_fields_noalloc",
+    "lbm_stream_probe",
 )
 
 
@@ -155,6 +156,8 @@ def lib():
             "lbm_reduce": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_stats)]),
             "lbm_fields": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_uint32, _dp, ctypes.c_size_t]),
             "lbm_fields_noalloc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_uint32, _dp, ctypes.c_size_t]),
+            "lbm_stream_probe": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_double)]),
             "lbm_set_report": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int32]),
             "lbm_series": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_stats), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]),
@@ -283,6 +286,13 @@ def lbm_fields_noalloc(ctx, slot, nx, ny, mask=63):
     buf = np.empty((len(names), ny, nx), dtype=np.float64)
     _check(lib().lbm_fields_noalloc(ctx, int(slot), int(mask), _ptr(buf), buf.size))
     return {n: buf[k] for k, n in enumerate(names)}
+
+
+def lbm_stream_probe(ctx, nbytes, pattern, launches=40):
+    """Microseconds per launch of the layout's streaming probe (lbm.h)."""
+    us = ctypes.c_double()
+    _check(lib().lbm_stream_probe(ctx, int(nbytes), int(pattern), int(launches), ctypes.byref(us)))
+    return us.value
 
 
 def lbm_set_report(ctx, slot, every, capacity):

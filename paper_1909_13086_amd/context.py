@@ -83,6 +83,9 @@ class Context:
         nx, ny = self._shape[slot]
         return L.lbm_fields_noalloc(self.h, slot, nx, ny, mask)
 
+    def stream_probe(self, nbytes, pattern, launches=40):
+        return L.lbm_stream_probe(self.h, nbytes, pattern, launches)
+
     def state_load(self, slot, f, g):
         L.lbm_state_load(self.h, slot, f, g)
 

@@ -359,6 +359,33 @@ hipError_t launch_reduce(const CavDev &c, int precision, double *partials, Stats
   return hipGetLastError();
 }
 
+// Streaming ceiling of the blocked lattice layout: each wavefront reads one
+// 64-cell chunk of 18 FP64 planes (9 KiB) and writes it to the other buffer
+// (the two-lattice pattern) or back into the same chunk (in place), with the
+// step kernels' order: workgroups of four wavefronts in contiguous bands per
+// XCD, walked backwards on odd launches.  No lattice arithmetic: it measures
+// what the memory system gives that access pattern.
+__global__ __launch_bounds__(256) void k_stream(const double *__restrict__ src, double *__restrict__ dst,
+                                                int64_t chunks, int back) {
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int64_t t = (int64_t)tile_of(blockIdx.x, gridDim.x, true, back != 0) * 4 + wid;
+  if (t >= chunks) return;
+  const double *a = src + t * (kPlanes * kWave) + lane;
+  double *b = dst + t * (kPlanes * kWave) + lane;
+  double v[kPlanes];
+#pragma unroll
+  for (int i = 0; i < kPlanes; ++i) v[i] = a[i * kWave];
+#pragma unroll
+  for (int i = 0; i < kPlanes; ++i) b[i * kWave] = v[i] + 1.0;
+}
+
+hipError_t launch_stream(const double *src, double *dst, int64_t chunks, int back, hipStream_t s) {
+  const int64_t blocks = (chunks + 3) / 4;
+  if (chunks < 1 || blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, chunks, back);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
   const size_t n = bytes / 4;

@@ -52,44 +52,39 @@ __host__ __device__ constexpr double wgt(int i) {
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
 
-// Rates and constants of one cavity, converted once per thread to the
-// arithmetic type R of the update.
-template <typename R>
-struct Coef {
-  R k0g, dk1g, dk2g;       // k0, k1 - k0, k2 - k0 for g
-  R k0f, dk1f, dk2f;       // same for f
-  R omk0g, omk0f;          // 1 - k0
-  R hk1f, hk2f;            // 1 - k1/2, 1 - k2/2 for the force terms
-  R Cp, inv_Cp, L, inv_L, rho0, inv_rho0, gb, Tm;
-  R c2[3];                 // 2 w_i Cp (Th - Tm) for w = 4/9 (unused), 1/9, 1/36
-  R darcy_c, darcy_eps;    // drag constants of the Darcy solid model
-
-  __device__ explicit Coef(const CavDev &c) {
-    k0g = R(c.k0g);
-    dk1g = R(c.k1g - c.k0g);
-    dk2g = R(c.k2g - c.k0g);
-    k0f = R(c.k0f);
-    dk1f = R(c.k1f - c.k0f);
-    dk2f = R(c.k2f - c.k0f);
-    omk0g = R(1.0 - c.k0g);
-    omk0f = R(1.0 - c.k0f);
-    hk1f = R(1.0 - 0.5 * c.k1f);
-    hk2f = R(1.0 - 0.5 * c.k2f);
-    Cp = R(c.Cp);
-    inv_Cp = R(c.inv_Cp);
-    L = R(c.latent);
-    inv_L = R(c.inv_latent);
-    rho0 = R(c.rho0);
-    inv_rho0 = R(c.inv_rho0);
-    gb = R(c.gbeta_rho0);
-    Tm = R(c.Tm);
-    c2[0] = R(2.0 * wgt(0) * c.Cp * c.dT);
-    c2[1] = R(2.0 * wgt(1) * c.Cp * c.dT);
-    c2[2] = R(2.0 * wgt(5) * c.Cp * c.dT);
-    darcy_c = R(c.darcy_c);
-    darcy_eps = R(c.darcy_eps);
+// The rates of a cavity in the arithmetic type R of the update, read from
+// its descriptor (computed on the host, Rates).  They are wavefront-uniform
+// and land in scalar registers.  VREG = true moves each into a vector
+// register instead: the fused kernels, whose walks hold many scalars of their
+// own, would otherwise spill the rates to vector-register lanes and read
+// them back with an instruction per use.
+template <typename R, bool VREG = false>
+struct Coef : Rates<R> {
+  __device__ explicit Coef(const CavDev &c) : Rates<R>(rates_of(c)) {
+    if constexpr (VREG) {
+      static_assert(sizeof(Rates<R>) % sizeof(R) == 0, "rates are an array of R");
+      R *p = reinterpret_cast<R *>(static_cast<Rates<R> *>(this));
+#pragma unroll
+      for (int i = 0; i < (int)(sizeof(Rates<R>) / sizeof(R)); ++i) p[i] = in_vgpr(p[i]);
+    }
   }
-  __device__ R anti(int i) const { return i == 0 ? c2[0] : (i <= 4 ? c2[1] : c2[2]); }
+
+ private:
+  __device__ static const Rates<R> &rates_of(const CavDev &c) {
+    if constexpr (sizeof(R) == 8)
+      return c.r64;
+    else
+      return c.r32;
+  }
+  // a copy of a uniform value in a vector register (removed if unused)
+  __device__ static R in_vgpr(R x) {
+    R y;
+    if constexpr (sizeof(R) == 8)
+      asm("v_mov_b64 %0, %1" : "=v"(y) : "s"(x));
+    else
+      asm("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
+    return y;
+  }
 };
 
 template <typename R>
@@ -98,85 +93,78 @@ __device__ __forceinline__ R sel(bool p, R a, R b) {
 }
 
 // Sec. 2 below Eq. (1): H = Cp T + fl L with isothermal melting at Tm, in
-// shifted form dH = H - Cp Tm, theta = T - Tm.
+// shifted form dH = H - Cp Tm, theta = T - Tm.  The latent part of the
+// enthalpy is dH clamped to [0, L]: fl is that part over L, and theta is what
+// lies outside it over Cp (exactly 0 in the mushy range).
 template <typename R>
 __device__ __forceinline__ void enthalpy_map(R dH, R L, R inv_L, R inv_Cp, R &fl, R &th) {
-  const bool solid = dH <= R(0);
-  const bool liquid = !solid && dH >= L;
-  fl = solid ? R(0) : (liquid ? R(1) : dH * inv_L);
-  th = solid ? dH * inv_Cp : (liquid ? (dH - L) * inv_Cp : R(0));
+  const R lat = fmin(fmax(dH, R(0)), L);
+  fl = fmin(fmax(dH * inv_L, R(0)), R(1));
+  th = (dH - lat) * inv_Cp;
 }
 
-// Relaxation of Eq. (2) for a pair of opposite populations (i, opp(i)).
-// With the combined first- and second-moment corrections a1, a2, Eq. (2)
-// reads p_i* = p_i - k0 (p_i - peq_i) - 3 w_i c_i.a1 - (9/2) w_i Q_i:a2,
-// Q_i = c_i c_i - I/3.  Under c -> -c the equilibrium splits into an even
-// part E and an odd part O, c.a1 changes sign and Q:a2 does not, so
-//   p_{+/-}* = (1 - k0) p_{+/-} + (k0 E - t2) +/- (k0 O - t1)
-// with t1 = 3 w c.a1 and t2 = (9/2) w Q:a2 taken for the "+" member.
+// Zeroth, first and second moments of nine populations, with the partial
+// sums of opposite pairs shared between them.
 template <typename R>
-__device__ __forceinline__ void relax_pair(R &pp, R &pm, R omk0, R k0, R E, R O, R t1, R t2) {
-  const R even = k0 * E - t2;
-  const R odd = k0 * O - t1;
-  pp = omk0 * pp + (even + odd);
-  pm = omk0 * pm + (even - odd);
-}
-
-// The same followed by partial bounce-back with solid fraction ns: each
-// member mixes its post-collision value with its partner's pre-collision one.
-template <typename R>
-__device__ __forceinline__ void relax_pair_pbb(R &pp, R &pm, R omk0, R k0, R E, R O, R t1, R t2,
-                                               R ns) {
-  const R pp0 = pp, pm0 = pm;
-  relax_pair<R>(pp, pm, omk0, k0, E, O, t1, t2);
-  pp = (R(1) - ns) * pp + ns * pm0;
-  pm = (R(1) - ns) * pm + ns * pp0;
-}
-
-// The four pairs of D2Q9 directions, "+" member first: (1, 3) along x,
-// (2, 4) along y, (5, 7) along (1, 1), (6, 8) along (-1, 1).  For each pair,
-// c.u, c.a1 and Q:a2 of the "+" member.
-template <typename R>
-struct PairTerms {
-  R cu[4], c1[4], qa[4];
-  __device__ PairTerms(R ux, R uy, R a1x, R a1y, R a2xx, R a2xy, R a2yy) {
-    constexpr R third = R(1.0 / 3.0), two_thirds = R(2.0 / 3.0);
-    cu[0] = ux;
-    cu[1] = uy;
-    cu[2] = ux + uy;
-    cu[3] = uy - ux;
-    c1[0] = a1x;
-    c1[1] = a1y;
-    c1[2] = a1x + a1y;
-    c1[3] = a1y - a1x;
-    const R d = two_thirds * (a2xx + a2yy);
-    qa[0] = two_thirds * a2xx - third * a2yy;
-    qa[1] = two_thirds * a2yy - third * a2xx;
-    qa[2] = d + R(2) * a2xy;
-    qa[3] = d - R(2) * a2xy;
+struct Moments {
+  R m0, jx, jy, pxx, pyy, pxy;
+  __device__ explicit Moments(const R (&p)[kQ]) {
+    const R s13 = p[1] + p[3], d13 = p[1] - p[3];
+    const R s24 = p[2] + p[4], d24 = p[2] - p[4];
+    const R s56 = p[5] + p[6], d56 = p[5] - p[6];
+    const R s78 = p[7] + p[8], d87 = p[8] - p[7];
+    const R diag = s56 + s78;
+    m0 = (p[0] + s13) + (s24 + diag);
+    jx = d13 + (d56 + d87);
+    jy = d24 + (s56 - s78);
+    pxx = s13 + diag;
+    pyy = s24 + diag;
+    pxy = d56 - d87;
   }
 };
-__device__ constexpr int pair_plus(int p) { return p == 0 ? 1 : (p == 1 ? 2 : (p == 2 ? 5 : 6)); }
-__device__ constexpr int pair_minus(int p) { return p == 0 ? 3 : (p == 1 ? 4 : (p == 2 ? 7 : 8)); }
-__device__ constexpr double pair_w(int p) { return p < 2 ? 1.0 / 9.0 : 1.0 / 36.0; }
+
+// Relaxation of Eq. (2) in pair form.  With the combined first- and
+// second-moment corrections a1, a2, Eq. (2) reads
+//   p_i* = (1 - k0) p_i + k0 peq_i - 3 w_i c_i.a1 - (9/2) w_i Q_i:a2,
+// Q_i = c_i c_i - I/3.  Under c -> -c the terms split into a part E that
+// is even (the even equilibrium part and the Q:a2 term) and a part O that is
+// odd (the odd equilibrium part and the c.a1 term), so the two members of an
+// opposite pair (i, opp(i)) are
+//   p_{+/-}* = (1 - k0) p_{+/-} + (E +/- O).
+// The four pairs, "+" member first: (1, 3) along x, (2, 4) along y, (5, 7)
+// along (1, 1), (6, 8) along (-1, 1); w = 1/9 on the axes, 1/36 on the
+// diagonals.  With the second-moment corrections given as a2/6, the Q:a2
+// parts of E, -(9/2) w Q_i:a2, are
+//   axis x: -(1/2)(2/3 a2xx - 1/3 a2yy) = -2 (a2xx/6) + a2yy/6, axis y alike;
+//   diagonals: -(1/8)(2/3 (a2xx + a2yy) +/- 2 a2xy)
+//            = -(1/2)(a2xx/6 + a2yy/6) -/+ (3/2)(a2xy/6);
+// and with v/3 = (k0 (first moment of the equilibrium) - a1)/3 the O parts,
+// 3 w c_i.v, are v_x/3, v_y/3 on the axes and (+/-v_x/3 + v_y/3)/4 on the
+// diagonals.  Each pair is relaxed as soon as its two terms exist, so few
+// temporaries are live at once.
+template <typename R>
+__device__ __forceinline__ void relax_pair(R &pp, R &pm, R omk0, R E, R O) {
+  pp = omk0 * pp + (E + O);
+  pm = omk0 * pm + (E - O);
+}
 
 // One B-TriRT collision of a cell, shifted populations in place.  MODEL is
 // the solid-phase treatment of the flow (kSolid*), fixed at compile time.
 template <typename R, int MODEL>
-__device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]) {
+__device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ]) {
   constexpr R third = R(1.0 / 3.0);
-  constexpr R w0 = R(4.0 / 9.0);
-  // (a) total enthalpy
+  // (a) total enthalpy (the other moments of g are taken in (e), so that
+  // they are not held through the flow part)
   const R dH = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-  // (b) temperature and liquid fraction
-  R fl, th;
-  enthalpy_map(dH, k.L, k.inv_L, k.inv_Cp, fl, th);
-  // (c) flow moments, buoyancy, velocity immobilised in the solid
-  const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const R Fb = k.gb * th;  // buoyancy, along +y
-  R ux, uy, Fx = R(0), Fy = Fb;
+  // (b) liquid fraction and Cp theta (the map of enthalpy_map: the latent part
+  // is dH clamped to [0, L], and Cp theta is what lies outside it)
+  const R lat = fmin(fmax(dH, R(0)), k.L);
+  const R fl = fmin(fmax(dH * k.inv_L, R(0)), R(1));
+  const R Cpth = dH - lat;
+  // (c) flow moments, buoyancy, momentum rho0 u immobilised in the solid
+  const Moments<R> mf(f);
+  const R Fb = k.gbc * Cpth;  // buoyancy rho0 g beta theta, along +y
+  R ux, uy, rux, ruy, Fx = R(0), Fy = Fb;
   if constexpr (MODEL == kSolidDarcy) {
     // rho0 u = j + (Fb - A rho0 u)/2, A = C (1 - fl)^2 / (fl^3 + eps): with
     // D = fl^3 + eps + C (1 - fl)^2 / 2, u = (fl^3 + eps)/D (j + Fb/2)/rho0
@@ -185,93 +173,91 @@ __device__ __forceinline__ void collide(const Coef<R> &k, R (&f)[kQ], R (&g)[kQ]
     const R fl3e = fl * fl * fl + k.darcy_eps;
     const R cm = k.darcy_c * ml * ml;
     const R rD = R(1) / (fl3e + R(0.5) * cm);
-    const R qy = jy + R(0.5) * Fb;
+    const R qy = mf.jy + R(0.5) * Fb;
     const R s = fl3e * rD * k.inv_rho0;
-    ux = s * jx;
+    ux = s * mf.jx;
     uy = s * qy;
-    Fx = -(cm * rD) * jx;
+    Fx = -(cm * rD) * mf.jx;
     Fy = Fb - (cm * rD) * qy;
+    rux = k.rho0 * ux;
+    ruy = k.rho0 * uy;
   } else {
-    // velocity scaled by the liquid fraction, or free (bounce-back model)
-    const R s = MODEL == kSolidPbb ? R(1) : fl;
-    ux = s * jx * k.inv_rho0;
-    uy = s * (jy + R(0.5) * Fb) * k.inv_rho0;
+    // rho0 u = j + F/2, scaled by the liquid fraction (or free: bounce-back model)
+    const R qy = mf.jy + R(0.5) * Fb;
+    rux = MODEL == kSolidPbb ? mf.jx : fl * mf.jx;
+    ruy = MODEL == kSolidPbb ? qy : fl * qy;
+    ux = k.inv_rho0 * rux;
+    uy = k.inv_rho0 * ruy;
   }
-  // (d) flow collision with the Hermite-projected force
+  // (d) flow collision with the Hermite-projected force:
+  //   a1 = (k1 - k0)(j - rho0 u) - (1 - k1/2) F,
+  //   a2 = (k2 - k0)(Pi - rho0 u u - drho I/3) - (1 - k2/2)(u F + F u)
+  // (Pi the second moment); the odd parts need k0 rho0 u - a1
+  // = k1 rho0 u - (k1 - k0) j + (1 - k1/2) F.
   {
-    const R d = (f[5] + f[6]) + (f[7] + f[8]);
-    const R pxx = (f[1] + f[3]) + d;
-    const R pyy = (f[2] + f[4]) + d;
-    const R pxy = (f[5] - f[6]) + (f[7] - f[8]);
-    const R r3 = drho * third;
-    const R m1x = jx - k.rho0 * ux, m1y = jy - k.rho0 * uy;
-    const R m2xx = pxx - (r3 + k.rho0 * ux * ux);
-    const R m2yy = pyy - (r3 + k.rho0 * uy * uy);
-    const R m2xy = pxy - k.rho0 * ux * uy;
-    // the force has an x part only under the drag
-    constexpr bool fx = MODEL == kSolidDarcy;
-    const R a1x = fx ? k.dk1f * m1x - k.hk1f * Fx : k.dk1f * m1x;
-    const R a1y = k.dk1f * m1y - k.hk1f * Fy;
-    const R a2xx = fx ? k.dk2f * m2xx - k.hk2f * (R(2) * ux * Fx) : k.dk2f * m2xx;
-    const R a2xy = k.dk2f * m2xy - k.hk2f * (fx ? ux * Fy + uy * Fx : ux * Fy);
-    const R a2yy = k.dk2f * m2yy - k.hk2f * (R(2) * uy * Fy);
-    const R uu15 = R(1.5) * (ux * ux + uy * uy);
-    const R feq0 = w0 * (drho - k.rho0 * uu15);
-    const R qa0 = -(a2xx + a2yy) * third;
-    const PairTerms<R> t(ux, uy, a1x, a1y, a2xx, a2xy, a2yy);
+    constexpr bool fx = MODEL == kSolidDarcy;  // the force has an x part only under the drag
+    const R rxx = rux * ux, ryy = ruy * uy;
+    const R r3 = mf.m0 * third;
+    const R hF = k.hk2f3 * Fy;
+    const R a6xx = fx ? k.dk2f6 * (mf.pxx - (r3 + rxx)) - k.hk2f3 * (ux * Fx)
+                      : k.dk2f6 * (mf.pxx - (r3 + rxx));
+    const R a6yy = k.dk2f6 * (mf.pyy - (r3 + ryy)) - hF * uy;
+    const R a6xy = k.dk2f6 * (mf.pxy - rux * uy) -
+                   R(0.5) * (fx ? hF * ux + k.hk2f3 * (uy * Fx) : hF * ux);
+    const R vx3 = fx ? (k.k1f3 * rux - k.dk1f3 * mf.jx) + k.hk1f3 * Fx : k.k1f3 * rux - k.dk1f3 * mf.jx;
+    const R vy3 = (k.k1f3 * ruy - k.dk1f3 * mf.jy) + k.hk1f3 * Fy;
+    // k0 w X with X = drho - (3/2) rho0 u.u is the equilibrium without its
+    // c.u terms; k0 (9/2) w rho0 (c.u)^2 adds the rest of its even part
+    const R b9 = k.k0f9 * (mf.m0 - R(1.5) * (rxx + ryy));
+    const R tr6 = a6xx + a6yy;
+    const R t36 = R(0.25) * b9 - R(0.5) * tr6;
+    const R rcu2 = (rux + ruy) * (ux + uy), rcu3 = (ruy - rux) * (uy - ux);
+    R pre[kQ];
     if constexpr (MODEL == kSolidPbb) {
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) pre[i] = f[i];
+    }
+    relax_pair<R>(f[1], f[3], k.omk0f, k.k0h * rxx + ((b9 - R(2) * a6xx) + a6yy), vx3);
+    relax_pair<R>(f[2], f[4], k.omk0f, k.k0h * ryy + ((b9 - R(2) * a6yy) + a6xx), vy3);
+    relax_pair<R>(f[5], f[7], k.omk0f, k.k0e * rcu2 + (t36 - R(1.5) * a6xy), R(0.25) * (vx3 + vy3));
+    relax_pair<R>(f[6], f[8], k.omk0f, k.k0e * rcu3 + (t36 + R(1.5) * a6xy), R(0.25) * (vy3 - vx3));
+    // rest population: k0 w0 X - (9/2) w0 Q_0:a2 = 4 (k0 X/9) + 4 (a2xx + a2yy)/6
+    const R f0 = k.omk0f * f[0] + R(4) * (b9 + tr6);
+    if constexpr (MODEL == kSolidPbb) {
+      // partial bounce-back: each member mixes its post-collision value with
+      // its partner's pre-collision one, weighted by the solid fraction
       const R ns = R(1) - fl;
-      f[0] = (R(1) - ns) * (k.omk0f * f[0] + (k.k0f * feq0 - R(4.5) * w0 * qa0)) + ns * f[0];
+      f[0] = (R(1) - ns) * f0 + ns * pre[0];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const R w = R(pair_w(p));
-        const R E = w * (drho + k.rho0 * (R(4.5) * t.cu[p] * t.cu[p] - uu15));
-        const R O = R(3) * w * k.rho0 * t.cu[p];
-        relax_pair_pbb<R>(f[pair_plus(p)], f[pair_minus(p)], k.omk0f, k.k0f, E, O,
-                          R(3) * w * t.c1[p], R(4.5) * w * t.qa[p], ns);
-      }
+      for (int i = 1; i < kQ; ++i) f[i] = (R(1) - ns) * f[i] + ns * pre[opp(i)];
     } else {
-      f[0] = k.omk0f * f[0] + (k.k0f * feq0 - R(4.5) * w0 * qa0);
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const R w = R(pair_w(p));
-        const R E = w * (drho + k.rho0 * (R(4.5) * t.cu[p] * t.cu[p] - uu15));
-        const R O = R(3) * w * k.rho0 * t.cu[p];
-        relax_pair<R>(f[pair_plus(p)], f[pair_minus(p)], k.omk0f, k.k0f, E, O, R(3) * w * t.c1[p],
-                      R(4.5) * w * t.qa[p]);
-      }
+      f[0] = f0;
     }
   }
-  // (e) enthalpy collision with the equilibrium of Eq. (3)
+  // (e) enthalpy collision with the equilibrium of Eq. (3):
+  //   geq_0 = dH - (1 - w0) Cp theta, geq_i = w_i (Cp theta + 3 Cp T c_i.u);
+  //   a1 = (k1 - k0)(q - Cp T u), a2 = (k2 - k0)(Pi - Cp theta I/3)
+  // (q, Pi the first and second moments of g); the odd parts need
+  // k0 Cp T u - a1 = k1 Cp T u - (k1 - k0) q.
   {
-    const R T = k.Tm + th;
-    const R CpT = k.Cp * T;
-    const R Cpth = k.Cp * th;
-    const R d = (g[5] + g[6]) + (g[7] + g[8]);
-    const R gx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const R gy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    const R qxx = (g[1] + g[3]) + d;
-    const R qyy = (g[2] + g[4]) + d;
-    const R qxy = (g[5] - g[6]) + (g[7] - g[8]);
-    const R a1x = k.dk1g * (gx - CpT * ux);
-    const R a1y = k.dk1g * (gy - CpT * uy);
-    const R a2xx = k.dk2g * (qxx - Cpth * third);
-    const R a2xy = k.dk2g * qxy;
-    const R a2yy = k.dk2g * (qyy - Cpth * third);
-    {
-      const R geq0 = dH - Cpth + w0 * Cpth;
-      const R qa0 = -(a2xx + a2yy) * third;
-      g[0] = k.omk0g * g[0] + (k.k0g * geq0 - R(4.5) * w0 * qa0);
-    }
-    const PairTerms<R> t(ux, uy, a1x, a1y, a2xx, a2xy, a2yy);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const R w = R(pair_w(p));
-      const R E = w * Cpth;
-      const R O = R(3) * w * CpT * t.cu[p];
-      relax_pair<R>(g[pair_plus(p)], g[pair_minus(p)], k.omk0g, k.k0g, E, O, R(3) * w * t.c1[p],
-                    R(4.5) * w * t.qa[p]);
-    }
+    const Moments<R> mg(g);
+    const R c3 = Cpth * third;
+    const R a6xx = k.dk2g6 * (mg.pxx - c3);
+    const R a6yy = k.dk2g6 * (mg.pyy - c3);
+    const R a6xy = k.dk2g6 * mg.pxy;
+    const R kT = k.k1g3 * (k.CpTm + Cpth);
+    const R vx3 = kT * ux - k.dk1g3 * mg.jx;
+    const R vy3 = kT * uy - k.dk1g3 * mg.jy;
+    const R b9 = k.k0g9 * Cpth;
+    const R tr6 = a6xx + a6yy;
+    const R t36 = R(0.25) * b9 - R(0.5) * tr6;
+    // rest population: k0 (dH - (5/9) Cp theta) + 4 (a2xx + a2yy)/6
+    const R g0 = k.omk0g * g[0] + ((k.k0g * dH - R(5) * b9) + R(4) * tr6);
+    relax_pair<R>(g[1], g[3], k.omk0g, (b9 - R(2) * a6xx) + a6yy, vx3);
+    relax_pair<R>(g[2], g[4], k.omk0g, (b9 - R(2) * a6yy) + a6xx, vy3);
+    relax_pair<R>(g[5], g[7], k.omk0g, t36 - R(1.5) * a6xy, R(0.25) * (vx3 + vy3));
+    relax_pair<R>(g[6], g[8], k.omk0g, t36 + R(1.5) * a6xy, R(0.25) * (vy3 - vx3));
+    g[0] = g0;
   }
 }
 
@@ -351,7 +337,7 @@ __device__ __forceinline__ void load_natural(const S *__restrict__ P, int64_t pl
 // Pre-collision populations gathered from the neighbours' swapped slots
 // (A-A parity 1); links from outside come back from the cell's own slot.
 template <typename S, typename R, bool NT = false>
-__device__ __forceinline__ void load_gather(const CavDev &c, const Coef<R> &k,
+__device__ __forceinline__ void load_gather(const CavDev &c, const Rates<R> &k,
                                             const S *__restrict__ P, int x, int y, int64_t idx,
                                             R (&f)[kQ], R (&g)[kQ]) {
   Nbr n;
@@ -370,7 +356,7 @@ __device__ __forceinline__ void load_gather(const CavDev &c, const Coef<R> &k,
 // Post-collision populations scattered to the neighbours' natural slots;
 // links leaving the cavity are reflected into the cell's opposite slot.
 template <typename S, typename R, bool NT = false>
-__device__ __forceinline__ void store_scatter(const CavDev &c, const Coef<R> &k,
+__device__ __forceinline__ void store_scatter(const CavDev &c, const Rates<R> &k,
                                               S *__restrict__ P, int x, int y, int64_t idx,
                                               const R (&f)[kQ], const R (&g)[kQ]) {
   Nbr n;
@@ -400,7 +386,7 @@ __device__ __forceinline__ void store_swapped(S *__restrict__ P, int64_t plane, 
 // back in the next step: each of its three upward links returns with
 // 2 w Cp (Th - Tm) - g_down, and adds twice its excess over w Cp (Th - Tm).
 template <typename R>
-__device__ __forceinline__ void add_strip_flux(const CavDev &c, const Coef<R> &k, int x,
+__device__ __forceinline__ void add_strip_flux(const CavDev &c, const Rates<R> &k, int x,
                                                const R (&g)[kQ]) {
   double q = 0.0;
 #pragma unroll
@@ -415,7 +401,7 @@ __device__ __forceinline__ void add_strip_flux(const CavDev &c, const Coef<R> &k
 // One lattice update of cell (x, y) for the given storage mode.
 //   mode 0: A-A even, mode 1: A-A odd, mode 2: two lattices (src -> dst)
 template <typename S, typename R, int MODEL, bool NT = false>
-__device__ __forceinline__ void update_cell(const CavDev &c, const Coef<R> &k, int mode, int x,
+__device__ __forceinline__ void update_cell(const CavDev &c, const Rates<R> &k, int mode, int x,
                                             int y) {
   const int64_t idx = cell_base(c, x, y);
   R f[kQ], g[kQ];

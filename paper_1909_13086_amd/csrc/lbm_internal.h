@@ -16,6 +16,27 @@ constexpr int kXcds = 8;
 // How the solid holds the flow still (values of LBM_SOLID_* in lbm.h).
 constexpr int kSolidScale = 0, kSolidDarcy = 1, kSolidPbb = 2;
 
+// The rates of Eq. (2) and the constants of one cavity in the combinations
+// that the collision multiplies by (its pair form, lbm_device.h), in the
+// arithmetic type R of the update.  Computed once on the host, so that no
+// kernel spends instructions on them; kernels read them from the cavity
+// descriptor into scalar registers.
+template <typename R>
+struct Rates {
+  R omk0g, omk0f;          // 1 - k0 for g and f
+  R k0g, k0g9;             // k0 and k0/9 for g
+  R dk1g3, k1g3, dk2g6;    // (k1 - k0)/3, k1/3, (k2 - k0)/6 for g
+  R k0f9, k0h, k0e;        // k0/9, k0/2, k0/8 for f
+  R dk1f3, k1f3, dk2f6;    // (k1 - k0)/3, k1/3, (k2 - k0)/6 for f
+  R hk1f3, hk2f3;          // (1 - k1/2)/3, (1 - k2/2)/3: force terms of f
+  R CpTm, L, inv_L, inv_Cp, rho0, inv_rho0;
+  R gbc;                   // rho0 g beta / Cp: buoyancy per unit of Cp theta
+  R c2[3];                 // 2 w_i Cp (Th - Tm) for w = 4/9, 1/9, 1/36
+  R darcy_c, darcy_eps;    // drag constants of the Darcy solid model
+
+  __host__ __device__ R anti(int i) const { return i == 0 ? c2[0] : (i <= 4 ? c2[1] : c2[2]); }
+};
+
 // Everything a kernel needs to advance or inspect one cavity.  Built on the
 // host from a validated case; passed by value (single cavity) or read from a
 // device array (batched launch).
@@ -38,7 +59,48 @@ struct CavDev {
   double darcy_c, darcy_eps;  // LBM_SOLID_DARCY: A = C (1 - fl)^2 / (fl^3 + eps)
   void *pop[2];        // population planes (pop[1] only for two lattices)
   double *cumq;        // per-column strip enthalpy summed over steps, nx doubles
+  Rates<double> r64;   // the rates for each arithmetic type (set_rates)
+  Rates<float> r32;
 };
+
+template <typename R>
+inline Rates<R> make_rates(const CavDev &c) {
+  Rates<R> k;
+  k.omk0g = R(1.0 - c.k0g);
+  k.omk0f = R(1.0 - c.k0f);
+  k.k0g = R(c.k0g);
+  k.k0g9 = R(c.k0g / 9.0);
+  k.dk1g3 = R((c.k1g - c.k0g) / 3.0);
+  k.k1g3 = R(c.k1g / 3.0);
+  k.dk2g6 = R((c.k2g - c.k0g) / 6.0);
+  k.k0f9 = R(c.k0f / 9.0);
+  k.k0h = R(c.k0f / 2.0);
+  k.k0e = R(c.k0f / 8.0);
+  k.dk1f3 = R((c.k1f - c.k0f) / 3.0);
+  k.k1f3 = R(c.k1f / 3.0);
+  k.dk2f6 = R((c.k2f - c.k0f) / 6.0);
+  k.hk1f3 = R((1.0 - 0.5 * c.k1f) / 3.0);
+  k.hk2f3 = R((1.0 - 0.5 * c.k2f) / 3.0);
+  k.CpTm = R(c.Cp * c.Tm);
+  k.L = R(c.latent);
+  k.inv_L = R(c.inv_latent);
+  k.inv_Cp = R(c.inv_Cp);
+  k.rho0 = R(c.rho0);
+  k.inv_rho0 = R(c.inv_rho0);
+  k.gbc = R(c.gbeta_rho0 * c.inv_Cp);
+  k.c2[0] = R(2.0 * (4.0 / 9.0) * c.Cp * c.dT);
+  k.c2[1] = R(2.0 * (1.0 / 9.0) * c.Cp * c.dT);
+  k.c2[2] = R(2.0 * (1.0 / 36.0) * c.Cp * c.dT);
+  k.darcy_c = R(c.darcy_c);
+  k.darcy_eps = R(c.darcy_eps);
+  return k;
+}
+
+// Fills the rate tables of a descriptor whose other fields are set.
+inline void set_rates(CavDev &c) {
+  c.r64 = make_rates<double>(c);
+  c.r32 = make_rates<float>(c);
+}
 
 // Batched launch: tiles of many cavities in one grid.
 struct BatchTile {
@@ -145,6 +207,8 @@ hipError_t launch_load(const CavDev &c, int precision, const double *f, const do
                        hipStream_t s);
 hipError_t launch_save(const CavDev &c, int precision, double *f, double *g, hipStream_t s);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// chunks of 18 x 64 doubles from src to dst (dst == src: in place); back: walk order reversed
+hipError_t launch_stream(const double *src, double *dst, int64_t chunks, int back, hipStream_t s);
 hipError_t launch_copy_stats(const StatsDev *src, StatsDev *dst, hipStream_t s);
 
 // Records the message returned by lbm_last_error() on this thread.

@@ -394,6 +394,7 @@ CavDev make_dev(const lbm_case *cs, const lbm_lattice &lat, const Layout &lay, v
   d.pop[0] = b;
   d.pop[1] = cs->pattern == LBM_PATTERN_AB ? b + lay.pop_bytes : nullptr;
   d.cumq = reinterpret_cast<double *>(b + lay.cumq_off);
+  set_rates(d);
   return d;
 }
 
@@ -1630,6 +1631,55 @@ struct CheckpointHeader {
 constexpr char kMagic[8] = {'B', 'T', 'R', 'I', 'R', 'T', 'C', 'K'};
 
 }  // namespace
+
+extern "C" int lbm_stream_probe(lbm_ctx *c, size_t bytes, int pattern, int launches, double *us) {
+  TraceRange range("lbm_stream_probe");
+  if (!c || !us) return fail(LBM_EINVAL, "NULL argument");
+  if (pattern != LBM_PATTERN_AA && pattern != LBM_PATTERN_AB) return fail(LBM_EINVAL, "pattern");
+  if (launches < 1 || launches > 100000) return fail(LBM_EINVAL, "launches out of range (1 .. 100000)");
+  const size_t chunk = (size_t)lbm::kPlanes * lbm::kWave * sizeof(double);
+  const int64_t chunks = (int64_t)(bytes / chunk);
+  if (chunks < 1 || chunks > ((int64_t)INT32_MAX - 3)) return fail(LBM_EINVAL, "bytes out of range");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t n = (size_t)chunks * chunk;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, n) != hipSuccess ||
+      (pattern == LBM_PATTERN_AB && hipMalloc(&b, n) != hipSuccess)) {
+    (void)hipGetLastError();
+    if (a) (void)hipFree(a);
+    return fail(LBM_ENOMEM, "stream probe buffers do not fit");
+  }
+  if (!b) b = a;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  float ms = 0.0f;
+  auto launch = [&](int i) {
+    // two lattices: odd launches copy back; both patterns walk backwards on odd launches
+    const bool odd = (i & 1) != 0;
+    const double *src = static_cast<const double *>(odd ? b : a);
+    double *dst = static_cast<double *>(odd ? a : b);
+    return lbm::launch_stream(src, dst, chunks, odd, c->stream);
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      lbm::launch_fill_zero(a, n, c->stream) != hipSuccess ||
+      (b != a && lbm::launch_fill_zero(b, n, c->stream) != hipSuccess) || launch(0) != hipSuccess ||
+      launch(1) != hipSuccess || hipEventRecord(e0, c->stream) != hipSuccess) {
+    rc = fail(LBM_EDEVICE, "stream probe set-up failed");
+  }
+  for (int i = 0; rc == LBM_OK && i < launches; ++i)
+    if (launch(i) != hipSuccess) rc = fail(LBM_EDEVICE, "stream probe launch failed");
+  if (rc == LBM_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(LBM_EDEVICE, "stream probe timing failed");
+  (void)hipStreamSynchronize(c->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (b != a) (void)hipFree(b);
+  (void)hipFree(a);
+  if (rc == LBM_OK) *us = 1e3 * (double)ms / launches;
+  return rc;
+}
 
 extern "C" size_t lbm_checkpoint_bytes(lbm_ctx *c, int slot) {
   if (check_slot(c, slot) != LBM_OK) return 0;

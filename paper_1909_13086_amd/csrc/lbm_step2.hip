@@ -126,7 +126,7 @@ __device__ __forceinline__ Col make_col(const CavDev &c, int x, int lane, int y0
 // First step of a loaded row: collision, plus the strip flux of a heated
 // bottom cell's first step.
 template <typename R, int MODEL>
-__device__ __forceinline__ void first_collide(const CavDev &c, const Coef<R> &k, const Col &q, int r,
+__device__ __forceinline__ void first_collide(const CavDev &c, const Rates<R> &k, const Col &q, int r,
                                               R (&f)[kQ], R (&g)[kQ]) {
   collide<R, MODEL>(k, f, g);
   if (r == 0 && q.strip_flux) add_strip_flux<R>(c, k, q.x, g);
@@ -143,7 +143,7 @@ __device__ __forceinline__ void zero_row(R (&f)[kQ], R (&g)[kQ]) {
 // inside the cavity, no link crosses a wall), then collided (result in pf,
 // pg).
 template <typename R, int D, bool WALLS, int MODEL>
-__device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k, const Col &q, int y,
+__device__ __forceinline__ void second_collide(const CavDev &c, const Rates<R> &k, const Col &q, int y,
                                                const R (&cf)[kQ], const R (&cg)[kQ],
                                                const R (&nf)[kQ], const R (&ng)[kQ],
                                                const R (&af)[3], const R (&ag)[3], R (&pf)[kQ],
@@ -183,6 +183,50 @@ __device__ __forceinline__ void second_collide(const CavDev &c, const Coef<R> &k
   collide<R, MODEL>(k, pf, pg);
 }
 
+// The same for the third step of the ring walk: row y's own populations are
+// read from its LDS ring slot where they are used (the centre populations,
+// and the reflected ones of links that crossed a wall), instead of being held
+// in registers.  slot points at this lane's value of population 0.
+template <typename R, int D, bool WALLS, int MODEL>
+__device__ __forceinline__ void third_collide(const CavDev &c, const Rates<R> &k, const Col &q, int y,
+                                              const R *slot, const R (&nf)[kQ], const R (&ng)[kQ],
+                                              const R (&af)[3], const R (&ag)[3], R (&pf)[kQ],
+                                              R (&pg)[kQ]) {
+  const bool xm_in = c.periodic_x || q.x - 1 >= 0;
+  const bool xp_in = c.periodic_x || q.x + 1 < c.nx;
+  const bool ym_in = c.periodic_y || y - 1 >= 0;
+  const bool yp_in = c.periodic_y || y + 1 < c.ny;
+  const bool hot = q.bottom_hot && y == 0;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int ex = cx(i), ey = cy(i);
+    R vf, vg;
+    if (ey == 0) {
+      vf = slot[i * kWave];
+      vg = slot[(kQ + i) * kWave];
+    } else if (ey == D) {
+      vf = af[along_slot<D>(i)];
+      vg = ag[along_slot<D>(i)];
+    } else {
+      vf = nf[i];
+      vg = ng[i];
+    }
+    vf = lane_from(vf, ex);
+    vg = lane_from(vg, ex);
+    const bool in_x = ex > 0 ? xm_in : (ex < 0 ? xp_in : true);
+    const bool in_y = ey > 0 ? ym_in : (ey < 0 ? yp_in : true);
+    if (WALLS && !(in_x && in_y)) {
+      // the link crossed a wall: it comes back from the cell itself
+      vf = slot[opp(i) * kWave];
+      vg = slot[(kQ + opp(i)) * kWave];
+      if (ey == 1 && hot) vg = k.anti(i) - vg;
+    }
+    pf[i] = vf;
+    pg[i] = vg;
+  }
+  collide<R, MODEL>(k, pf, pg);
+}
+
 // Post-collision populations of an interior cell pushed to its neighbours'
 // natural slots: three row bases (wavefront-uniform) and three column
 // offsets within a row, so every address is a row pointer plus a 32-bit
@@ -211,7 +255,7 @@ __device__ __forceinline__ void store_interior(const CavDev &c, S *__restrict__ 
 // Stores of an owned cell's second step (and its strip flux).
 // FLUX = false: the strip flux of this step was already counted.
 template <typename S, typename R, bool WALLS = true, bool FLUX = true>
-__device__ __forceinline__ void emit(const CavDev &c, const Coef<R> &k, S *__restrict__ B, const Col &q,
+__device__ __forceinline__ void emit(const CavDev &c, const Rates<R> &k, S *__restrict__ B, const Col &q,
                                      int y, const R (&pf)[kQ], const R (&pg)[kQ]) {
   if (q.owner) {
     if constexpr (WALLS) {
@@ -250,7 +294,7 @@ __device__ __forceinline__ void slide(R (&af)[3], R (&ag)[3], R (&cf)[kQ], R (&c
 // segments walking in opposite directions reach the two halo rows they share
 // at the same point of their walks, so the second reader finds them in L2.
 template <typename S, typename R, int D, int MODEL>
-__device__ __forceinline__ void walk_direct(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+__device__ __forceinline__ void walk_direct(const CavDev &c, const Rates<R> &k, const S *__restrict__ A,
                                             S *__restrict__ B, const Col &q, int y0, int y1) {
   auto first_step = [&](int r, R (&f)[kQ], R (&g)[kQ]) {
     // zeros when the row or column does not exist; such values are never used
@@ -376,7 +420,7 @@ __device__ __forceinline__ void read_row(const S *buf, int lane, R (&f)[kQ], R (
 // row k is read and collided; it is waited for before the stores of that
 // iteration are issued, so the stores never delay a later wait.
 template <typename S, typename R, int D, bool WALLS, int MODEL>
-__device__ __forceinline__ void walk_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+__device__ __forceinline__ void walk_staged(const CavDev &c, const Rates<R> &k, const S *__restrict__ A,
                                             S *__restrict__ B, const Col &q, int y0, int y1, int x0,
                                             S *bufs) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -440,7 +484,7 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
   const int y0 = seg * seg_rows;
   const int y1 = min(y0 + seg_rows, c.ny);
   const Col q = make_col(c, x0 - 1 + lane, lane, y0);
-  const Coef<R> k(c);
+  const Coef<R, true> k(c);
   const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
   S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
   const bool down = (order & 4) && (seg & 1);
@@ -505,7 +549,7 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
 // launch whose cavity has two steps left); its strip flux is counted where
 // level 2 is computed.
 template <typename S, typename R, int D, bool WALLS, int MODEL, int STEPS = 3>
-__device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+__device__ __forceinline__ void walk3_staged(const CavDev &c, const Rates<R> &k, const S *__restrict__ A,
                                              S *__restrict__ B, const Col &q, int y0, int y1, int x0,
                                              S *bufs) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -588,7 +632,7 @@ __device__ __forceinline__ void walk3_staged(const CavDev &c, const Coef<R> &k, 
 // column of a slot, and LDS operations of a wavefront complete in order, so
 // no barrier is needed.
 template <typename S, typename R, int D, bool WALLS, int MODEL, int STEPS = 3, bool PIPE = true>
-__device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, const S *__restrict__ A,
+__device__ __forceinline__ void walk3_ring(const CavDev &c, const Rates<R> &k, const S *__restrict__ A,
                                            S *__restrict__ B, const Col &q, int y0, int y1, R *ring) {
   const int lane = threadIdx.x & (kWave - 1);
   auto slot = [&](int r) { return ring + (r & 1) * (kPlanes * kWave) + lane; };
@@ -674,10 +718,9 @@ __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, co
       R a2f[3], a2g[3];
       get_along(y - D, a2f, a2g);
       put(y + D, n2f, n2g);  // the slot of row y-D
-      R c2f[kQ], c2g[kQ], pf[kQ], pg[kQ];
-      get(y, c2f, c2g);
+      R pf[kQ], pg[kQ];
       if constexpr (PIPE && decltype(load_next)::value) load1(y + 3 * D, n1f, n1g);
-      second_collide<R, D, WALLS, MODEL>(c, k, q, y, c2f, c2g, n2f, n2g, a2f, a2g, pf, pg);
+      third_collide<R, D, WALLS, MODEL>(c, k, q, y, slot(y), n2f, n2g, a2f, a2g, pf, pg);
       emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
     } else {
       R c2f[kQ], c2g[kQ];
@@ -694,7 +737,7 @@ __device__ __forceinline__ void walk3_ring(const CavDev &c, const Coef<R> &k, co
 
 // The three-step walk for either precision, direction and wall case.
 template <typename S, typename R, int MODEL, int STEPS, bool PIPE = false>
-__device__ __forceinline__ void walk3(bool down, bool inner, const CavDev &c, const Coef<R> &k,
+__device__ __forceinline__ void walk3(bool down, bool inner, const CavDev &c, const Rates<R> &k,
                                       const S *__restrict__ A, S *__restrict__ B, const Col &q, int y0,
                                       int y1, int x0, R *mine) {
   if constexpr (sizeof(R) == 8) {
@@ -801,7 +844,7 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step2_batch(const CavDev *__restr
     c.parity ^= (launch_index & 1);
     const int y0 = it.y0;
     const int y1 = min(y0 + seg_rows, c.ny);
-    const Coef<R> k(c);
+    const Coef<R, true> k(c);
     const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
     S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
     if (2 * launch_index + 2 <= a) {
@@ -871,7 +914,7 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_step3_batch(const CavDev *__restr
     c.parity ^= (launch_index & 1);
     const int y0 = it.y0;
     const int y1 = min(y0 + seg_rows, c.ny);
-    const Coef<R> k(c);
+    const Coef<R, true> k(c);
     const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
     S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
     const Col q = make_col<2>(c, it.x0 - 2 + lane, lane, y0);

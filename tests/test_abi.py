@@ -120,6 +120,8 @@ def test_context_calls_reject_a_null_context():
     assert lib.lbm_get_fusion(None, 0, ctypes.byref(n), ctypes.byref(seg)) == P.LBM_EINVAL
     assert lib.lbm_set_fusion(None, 0, 3, 4) == P.LBM_EINVAL
     assert lib.lbm_set_group_bytes(None, 1 << 30) == P.LBM_EINVAL
+    us = ctypes.c_double()
+    assert lib.lbm_stream_probe(None, 1 << 20, P.LBM_PATTERN_AB, 4, ctypes.byref(us)) == P.LBM_EINVAL
 
 
 class _CkptHeader(__import__("ctypes").Structure):
