@@ -197,13 +197,13 @@ def fp32_variant(P, steps, path="ab"):
     case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED,
                 pattern=P.LBM_PATTERN_AA if path == "aa" else P.LBM_PATTERN_AB)
     ctx = P.Context(device=0, max_slots=1)
-    if path != "aa":
-        ctx.set_fusion(P.LBM_FP32_SHIFTED, PATHS[path]["per_launch"])
-    slot = ctx.add(case)
+    if path == "ab2":
+        ctx.set_fusion(P.LBM_FP32_SHIFTED, 2)
+    slot = ctx.add(case)  # "ab": the default fusion for the cavity's size
     ctx.step(slot, 100)
     ms = time_steps(P, ctx, slot, steps)
     st = ctx.reduce(slot)
-    fuse, seg = ctx.get_fusion(P.LBM_FP32_SHIFTED)
+    fuse, seg = ctx.slot_fusion(slot)
     ctx.close()
     cells = case["nx"] * case["ny"]
     mlups = cells * steps / (ms * 1e-3) / 1e6
@@ -222,7 +222,8 @@ def fp32_variant(P, steps, path="ab"):
 def hbm_bound_variant(P, steps=240):
     """The same cavity physics on a 4096x2048 lattice, whose working set (1.2 GB
     FP64 and 604 MB FP32 in place, twice that on two lattices) is far above the
-    256 MB Infinity Cache: the HBM-bound regime, in place and two-step."""
+    256 MB Infinity Cache: the HBM-bound regime, in place and with the default
+    fusion (three steps per launch in FP64, four in FP32)."""
     from btrirt_workloads import large_cavity
     out = {}
     for pattern, pname in ((P.LBM_PATTERN_AA, "in_place"), (P.LBM_PATTERN_AB, "fused")):
@@ -231,7 +232,7 @@ def hbm_bound_variant(P, steps=240):
             ctx = P.Context(device=0, max_slots=1)
             slot = ctx.add(case)
             ctx.step(slot, 12)
-            fuse = ctx.get_fusion(prec)[0] if pattern == P.LBM_PATTERN_AB else 1
+            fuse = ctx.slot_fusion(slot)[0]
             ms = time_steps(P, ctx, slot, steps)
             ctx.close()
             cells = 4096 * 2048

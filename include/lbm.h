@@ -273,15 +273,15 @@ enum {
  * Results do not depend on the tile or the flags. */
 int lbm_set_launch(lbm_ctx *c, int precision, int bx, int by, int cpl, int flags);
 int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *flags);
-/* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2 or
- * 3 a single launch advances a LBM_PATTERN_AB slot by that many steps,
- * reading its lattice once and writing the other once.  Each wavefront walks
- * a strip of 62 (two steps) or 60 (three steps) columns along a segment of
- * segment_rows rows, 1 to 64, keeping three-row windows of the intermediate
- * steps in registers (FP64 three-step launches keep the second window in
- * LDS and load rows directly; the LBM_LAUNCH_STAGED flag applies to
- * two-step launches).
- * Segment rows are stored per depth (2 and 3); segment_rows = 0 keeps the
+/* Temporal blocking of the two-lattice pattern: with steps_per_launch = 2, 3
+ * or (FP32 only) 4 a single launch advances a LBM_PATTERN_AB slot by that
+ * many steps, reading its lattice once and writing the other once.  Each
+ * wavefront walks a strip of 62 (two steps), 60 (three) or 58 (four) columns
+ * along a segment of segment_rows rows, 1 to 64, keeping three-row windows
+ * of the intermediate steps in registers (FP64 three-step launches keep the
+ * second window in LDS and load rows directly; the LBM_LAUNCH_STAGED flag
+ * applies to two-step launches).  Batched launches fuse at most three steps.
+ * Segment rows are stored per depth (2, 3 and 4); segment_rows = 0 keeps the
  * stored value.  lbm_get_fusion returns the segment rows of the current
  * depth.  Launches never fuse steps across a report step, and step counts
  * that are not a multiple end with shorter launches.  Batched launches
@@ -290,12 +290,13 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * launch in segments of 6 rows; two-step segments of 2 rows (FP64) or 4
  * rows (FP32).  Until lbm_set_fusion or lbm_autotune
  * sets it, the default follows each cavity's size: FP64 cavities below 2^20
- * cells take two steps per launch, three-step segments shrink to 4, 2 or 1
- * rows until a launch has at least 1024 wavefronts (lbm_slot_fusion shows
- * the result), and batched launches choose their segment rows per cache
+ * cells take two steps per launch, FP32 cavities of 2^21 cells or more take
+ * four, three- and four-step segments shrink to 4, 2 or 1 rows until a
+ * launch has at least 1024 wavefronts (lbm_slot_fusion shows the result), and batched launches choose their segment rows per cache
  * group so that the group's segments fill the device's wavefronts evenly;
  * lbm_get_fusion returns the nominal values.  LBM_EINVAL for
- * steps_per_launch outside 1..3 or segment_rows outside 0..64. */
+ * steps_per_launch outside 1..4 (4 with LBM_FP64) or segment_rows outside
+ * 0..64. */
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows);
 int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segment_rows);
 /* Steps per captured HIP graph replayed by lbm_step (0 = plain launches). */
@@ -303,13 +304,14 @@ int lbm_set_graph_chunk(lbm_ctx *c, int chunk);
 /* Times the candidates on a scratch cavity of the given size and precision
  * and selects the fastest: block shape, rows per lane and walk flags of the
  * one-step kernels, segment rows and staged or direct rows of the two-step
- * kernel, segment rows of the three-step kernel, and then two or three steps
- * per launch by the time per step (unless the context runs single steps)
+ * kernel, segment rows of the three-step kernel (and in FP32 of the four-step
+ * kernel), and then two, three or four steps per launch by the time per step
+ * (unless the context runs single steps)
  * (lbm_set_launch, lbm_set_fusion).  When cache_path is not NULL the choice is
  * recorded there (JSON, one entry per precision and power-of-two size class:
  * bx, by, cpl, flags, us per one-step launch, segment rows and us per launch
- * of the two-step kernel, the same of the three-step kernel) and a cached
- * entry is reused. */
+ * of the two-step kernel, the same of the three-step kernel and in FP32 of
+ * the four-step kernel) and a cached entry is reused. */
 int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const char *cache_path);
 /* Measurement aid: the streaming ceiling of the lattice layout, against which
  * the step kernels' memory rate is read (no lattice arithmetic).  Allocates

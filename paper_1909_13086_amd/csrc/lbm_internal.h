@@ -116,14 +116,16 @@ struct LaunchCfg {
   int reverse = 1;  // walk tiles backwards on odd storage parity
   int zigzag = 1;   // two-step kernel: odd segments walked downwards
   int staged = 1;   // two-step kernel: rows copied into LDS one row ahead
-  int fuse = 2;     // steps per launch of the two-lattice pattern (1, 2 or 3)
+  int fuse = 2;     // steps per launch of the two-lattice pattern (1, 2, 3, or 4 in FP32)
   int seg = 4;      // rows per wavefront segment of the two-step kernel
   int seg3 = 6;     // rows per wavefront segment of the three-step kernel
+  int seg4 = 6;     // rows per wavefront segment of the four-step kernel (FP32)
   int adapt = 1;    // default fusion: depth and three-step segments follow the cavity size
 };
 constexpr int kMaxSegmentRows = 64;
 constexpr int kStripCols = kWave - 2;   // owned columns of a two-step wavefront
 constexpr int kStrip3Cols = kWave - 4;  // owned columns of a three-step wavefront
+constexpr int kStrip4Cols = kWave - 6;  // owned columns of a four-step wavefront
 
 // Defaults per precision, the fastest measured on MI355X at 2048x1024 and
 // 4096x2048: three steps per launch in segments of 6 rows; two-step launches
@@ -173,6 +175,8 @@ hipError_t launch_step2(const CavDev &c, int precision, const LaunchCfg &cfg, hi
 // Three steps per launch (two-lattice pattern): FP32 stages rows through LDS,
 // FP64 keeps its level-2 window there and loads rows directly.
 hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
+// four steps per launch, FP32 only (hipErrorInvalidValue for FP64)
+hipError_t launch_step4(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s);
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
 // entries.  A header that is empty or points outside them advances nothing
 // and sets *err_dev to kErrBatchHeader, which the host reports as an error.

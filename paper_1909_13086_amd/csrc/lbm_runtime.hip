@@ -454,13 +454,17 @@ int enqueue_one_step(lbm_ctx *c, Slot &s) {
 // Launch configuration of a slot.  While the fusion is the default (not set
 // by lbm_set_fusion or lbm_autotune) it follows the cavity size, as measured
 // on MI355X: FP64 cavities below 2^20 cells take two steps per launch (the
-// three-step kernel wins only on larger ones), and three-step segments
-// shrink (6, 4, 2, 1 rows) until the launch has at least 1024 wavefronts,
-// so small cavities still fill the GPU.
+// three-step kernel wins only on larger ones), FP32 cavities of 2^21 cells
+// or more take four (below, where the lattices sit in the Infinity Cache,
+// three are faster), and three- and four-step segments shrink (6, 4, 2, 1
+// rows) until the launch has at least 1024 wavefronts, so small cavities
+// still fill the GPU.
 LaunchCfg slot_launch(const lbm_ctx *c, const Slot &s) {
   LaunchCfg L = c->launch[s.cs.precision];
   if (!L.adapt || s.cs.pattern != LBM_PATTERN_AB) return L;
   if (L.fuse == 3 && s.cs.precision == LBM_FP64 && (int64_t)s.cs.nx * s.cs.ny < (int64_t)1 << 20) L.fuse = 2;
+  if (L.fuse == 3 && s.cs.precision == LBM_FP32_SHIFTED && (int64_t)s.cs.nx * s.cs.ny >= (int64_t)1 << 21)
+    L.fuse = 4;
   if (L.fuse == 3) {
     const int64_t strips = (s.cs.nx + lbm::kStrip3Cols - 1) / lbm::kStrip3Cols;
     for (int seg : {6, 4, 2, 1}) {
@@ -469,20 +473,29 @@ LaunchCfg slot_launch(const lbm_ctx *c, const Slot &s) {
       if (strips * ((s.cs.ny + seg - 1) / seg) >= 1024) break;
     }
   }
+  if (L.fuse == 4) {
+    const int64_t strips = (s.cs.nx + lbm::kStrip4Cols - 1) / lbm::kStrip4Cols;
+    for (int seg : {6, 4, 2, 1}) {
+      if (seg > L.seg4) continue;
+      L.seg4 = seg;
+      if (strips * ((s.cs.ny + seg - 1) / seg) >= 1024) break;
+    }
+  }
   return L;
 }
 
-// Steps per launch of a slot: two-lattice slots may advance two or three
-// steps per launch, in-place slots one.
+// Steps per launch of a slot: two-lattice slots may advance two, three or
+// (FP32) four steps per launch, in-place slots one.
 int steps_per_launch(const lbm_ctx *c, const Slot &s) {
   return s.cs.pattern == LBM_PATTERN_AB ? slot_launch(c, s).fuse : 1;
 }
 
-// One launch advancing the state by m steps (1, 2 or 3, at most the slot's
+// One launch advancing the state by m steps (1 to 4, at most the slot's
 // steps per launch).  Every launch moves the state to the other lattice of a
 // two-lattice slot; in place it flips the A-A parity.
 hipError_t launch_steps(const lbm_ctx *c, const Slot &s, const CavDev &d, int m) {
   const LaunchCfg L = slot_launch(c, s);
+  if (m == 4) return lbm::launch_step4(d, s.cs.precision, L, c->stream);
   if (m == 3) return lbm::launch_step3(d, s.cs.precision, L, c->stream);
   if (m == 2) return lbm::launch_step2(d, s.cs.precision, L, c->stream);
   return lbm::launch_step(d, s.cs.precision, L, c->stream);
@@ -497,10 +510,11 @@ int enqueue_steps(lbm_ctx *c, Slot &s, int m) {
 
 // Steps of the next launch when `left` steps remain before the next stop
 // (a report or the end of the request): the slot's steps per launch, fewer
-// at the end, and two instead of three when four remain (two two-step
-// launches cost less than a three-step and a single step).
+// at the end, and one fewer when one more than that remains, so that no
+// single step is left over (four steps as two and two, five as three and
+// two: two fused launches cost less than a deep one and a single step).
 int64_t next_launch_steps(int F, int64_t left) {
-  if (F == 3 && left == 4) return 2;
+  if (F >= 3 && left == F + 1) return F - 1;
   return std::min<int64_t>(F, left);
 }
 
@@ -602,8 +616,9 @@ constexpr int kStrip2Cols = lbm::kStripCols;
 // or three-step segments) and solid model; each has a {first, count} header.
 constexpr int kLaunchKinds = 2 * 3 * 3;
 int launch_bit(int prec, int kind, int model) { return (prec * 3 + kind) * 3 + model; }
-// kind of a slot's batched launches: its steps per launch - 1
-int batch_kind(const lbm_ctx *c, const Slot &s) { return steps_per_launch(c, s) - 1; }
+// kind of a slot's batched launches: its steps per launch - 1 (batched
+// launches fuse at most three steps; a four-step slot takes three there)
+int batch_kind(const lbm_ctx *c, const Slot &s) { return std::min(steps_per_launch(c, s), 3) - 1; }
 int hdr_index(int g, int prec, int kind, int model) {
   return (g * kLaunchKinds + launch_bit(prec, kind, model)) * 2;
 }
@@ -1315,13 +1330,16 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
 int lbm_set_fusion(lbm_ctx *c, int precision, int steps_per_launch, int segment_rows) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
-  if (steps_per_launch < 1 || steps_per_launch > 3 || segment_rows < 0 ||
+  if (steps_per_launch < 1 || steps_per_launch > 4 || segment_rows < 0 ||
       segment_rows > lbm::kMaxSegmentRows)
-    return fail(LBM_EINVAL, "steps per launch in {1, 2, 3}, segment rows in 0..64");
+    return fail(LBM_EINVAL, "steps per launch in {1, 2, 3, 4}, segment rows in 0..64");
+  if (steps_per_launch == 4 && precision != LBM_FP32_SHIFTED)
+    return fail(LBM_EINVAL, "four steps per launch are FP32 only");
   LaunchCfg &L = c->launch[precision];
   L.fuse = steps_per_launch;
   L.adapt = 0;
-  if (segment_rows > 0) (steps_per_launch == 3 ? L.seg3 : L.seg) = segment_rows;
+  if (segment_rows > 0)
+    (steps_per_launch == 4 ? L.seg4 : (steps_per_launch == 3 ? L.seg3 : L.seg)) = segment_rows;
   for (auto &s : c->slots) drop_graphs(s);
   c->batch.dirty = true;  // item lists depend on the fusion
   drop_batch_graph(c);
@@ -1333,7 +1351,7 @@ int lbm_get_fusion(lbm_ctx *c, int precision, int *steps_per_launch, int *segmen
   if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) return fail(LBM_EINVAL, "precision");
   const LaunchCfg &L = c->launch[precision];
   *steps_per_launch = L.fuse;
-  *segment_rows = L.fuse == 3 ? L.seg3 : L.seg;
+  *segment_rows = L.fuse == 4 ? L.seg4 : (L.fuse == 3 ? L.seg3 : L.seg);
   return LBM_OK;
 }
 
@@ -1365,7 +1383,7 @@ int lbm_slot_fusion(lbm_ctx *c, int slot, int *steps, int *rows) {
   const Slot &s = c->slots[slot];
   const LaunchCfg L = slot_launch(c, s);
   *steps = steps_per_launch(c, s);
-  *rows = *steps == 3 ? L.seg3 : L.seg;
+  *rows = *steps == 4 ? L.seg4 : (*steps == 3 ? L.seg3 : L.seg);
   return LBM_OK;
 }
 
@@ -1474,17 +1492,27 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   const std::string key = size_class(precision, nx, ny);
   auto cache = read_cache(cache_path);
   auto it = cache.find(key);
-  // entries without the three-step timing (an older format) are tuned again
-  if (it != cache.end() && it->second.size() >= 9) {
+  // the fastest depth per step among two, three and (FP32) four steps per
+  // launch, unless the caller runs single steps
+  auto pick = [&](int fuse, double us2, double us3, double us4) {
+    if (fuse == 1) return 1;
+    int f = us3 / 3 < us2 / 2 ? 3 : 2;
+    if (precision == LBM_FP32_SHIFTED && us4 / 4 < (f == 3 ? us3 / 3 : us2 / 2)) f = 4;
+    return f;
+  };
+  // entries without the three-step timing, or FP32 entries without the
+  // four-step timing (older formats), are tuned again
+  const size_t need = precision == LBM_FP32_SHIFTED ? 11 : 9;
+  if (it != cache.end() && it->second.size() >= need) {
     const std::vector<double> &v = it->second;
     const int fuse = c->launch[precision].fuse;
     int rc = lbm_set_launch(c, precision, (int)v[0], (int)v[1], (int)v[2], (int)v[3]);
     if (rc == LBM_OK) {
-      // the faster of two and three steps per launch, per step, unless the
-      // caller runs single steps
       rc = lbm_set_fusion(c, precision, 2, (int)v[5]);
       if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, 3, (int)v[7]);
-      if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, fuse == 1 ? 1 : (v[8] / 3 < v[6] / 2 ? 3 : 2), 0);
+      if (rc == LBM_OK && need == 11) rc = lbm_set_fusion(c, precision, 4, (int)v[9]);
+      if (rc == LBM_OK)
+        rc = lbm_set_fusion(c, precision, pick(fuse, v[6], v[8], need == 11 ? v[10] : 1e30), 0);
     }
     return rc;
   }
@@ -1589,6 +1617,25 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
       best_seg3 = seg;
     }
   }
+  // four steps per launch (FP32): segment rows (rows always staged)
+  int best_seg4 = saved.seg4;
+  float best4_ms = 1e30f;
+  if (precision == LBM_FP32_SHIFTED) {
+    for (int seg : segs3) {
+      if (rc != LBM_OK) break;
+      LaunchCfg cfg = best;
+      cfg.zigzag = 1;
+      cfg.seg4 = seg;
+      float ms = 0.0f;
+      rc = time_launches(c, two, e0, e1, reps,
+                         [&](const CavDev &d) { return lbm::launch_step4(d, precision, cfg, c->stream); },
+                         &ms);
+      if (rc == LBM_OK && ms < best4_ms) {
+        best4_ms = ms;
+        best_seg4 = seg;
+      }
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(c->stream);
@@ -1601,16 +1648,23 @@ extern "C" int lbm_autotune(lbm_ctx *c, int precision, int nx, int ny, const cha
   best.staged = best_staged;
   const int best_flags = flags_of(best);
   // entry: bx, by, cpl, flags, us per one-step launch, segment rows and us
-  // per launch of the two-step kernel, the same of the three-step kernel
+  // per launch of the two-step kernel, the same of the three-step kernel and
+  // (FP32) of the four-step kernel
   cache[key] = {(double)best.bx, (double)best.by, (double)best.cpl, (double)best_flags,
                 1000.0 * best_ms, (double)best_seg, 1000.0 * best2_ms, (double)best_seg3,
                 1000.0 * best3_ms};
+  if (precision == LBM_FP32_SHIFTED) {
+    cache[key].push_back((double)best_seg4);
+    cache[key].push_back(1000.0 * best4_ms);
+  }
   write_cache(cache_path, cache);
   rc = lbm_set_launch(c, precision, best.bx, best.by, best.cpl, best_flags);
   if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, 2, best_seg);
   if (rc == LBM_OK) rc = lbm_set_fusion(c, precision, 3, best_seg3);
+  if (rc == LBM_OK && precision == LBM_FP32_SHIFTED) rc = lbm_set_fusion(c, precision, 4, best_seg4);
   if (rc == LBM_OK)
-    rc = lbm_set_fusion(c, precision, saved.fuse == 1 ? 1 : (best3_ms / 3 < best2_ms / 2 ? 3 : 2), 0);
+    rc = lbm_set_fusion(c, precision,
+                        pick(saved.fuse, 1000.0 * best2_ms, 1000.0 * best3_ms, 1000.0 * best4_ms), 0);
   return rc;
 }
 

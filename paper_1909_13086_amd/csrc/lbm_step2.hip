@@ -622,6 +622,153 @@ __device__ __forceinline__ void walk3_staged(const CavDev &c, const Rates<R> &k,
   }
 }
 
+// ---- four steps per launch (FP32) ----------------------------------------
+//
+// The three-step walk one level deeper, for FP32 only (its three register
+// windows fit the register file; FP64's do not): a wavefront owns 58 columns
+// (lanes 3 .. 60; three halo columns each side) and a segment of `seg` rows;
+// iteration y of the walk computes level 1 of row y+3D (from the row staged
+// in LDS), level 2 of row y+2D, level 3 of row y+D and level 4 of row y,
+// which is stored.  Level m is correct on lanes m-1 .. 64-m, which is all
+// level m+1 of the owned lanes reads.  Rows are staged through the LDS double
+// buffer one row ahead, as in the other walks.  Each level is the single-step
+// update, so a launch equals four single two-lattice steps bit for bit; the
+// strip flux of row 0 is counted at every level by the segment that owns it.
+template <typename S, typename R, int D, bool WALLS, int MODEL>
+__device__ __forceinline__ void walk4_staged(const CavDev &c, const Rates<R> &k, const S *__restrict__ A,
+                                             S *__restrict__ B, const Col &q, int y0, int y1, int x0,
+                                             S *bufs) {
+  static_assert(sizeof(R) == 4, "four steps per launch are FP32 only");
+  const int lane = threadIdx.x & (kWave - 1);
+  const CopyLanes L = copy_lanes<S, 3>(c, x0 - 3, lane);
+  auto buf = [&](int b) { return bufs + b * (kPlanes * kWave); };
+  auto issue = [&](int r, int b) {
+    if (row_real<3>(c, r)) copy_row<S, 3>(c, A, L, r, buf(b));
+  };
+  auto level1 = [&](int r, int b, R (&f)[kQ], R (&g)[kQ]) {
+    if (!(row_real<3>(c, r) && q.real)) {
+      zero_row(f, g);
+      return;
+    }
+    read_row<S, R>(buf(b), lane, f, g);
+    first_collide<R, MODEL>(c, k, q, r, f, g);
+  };
+  // levels 2 and 3 of row r from the window below them, with the strip flux
+  // of row 0 (counted once per level by the segment that owns row 0)
+  auto next_level = [&](int r, const R (&cf)[kQ], const R (&cg)[kQ], const R (&nf)[kQ],
+                        const R (&ng)[kQ], const R (&af)[3], const R (&ag)[3], R (&f)[kQ], R (&g)[kQ]) {
+    second_collide<R, D, WALLS, MODEL>(c, k, q, r, cf, cg, nf, ng, af, ag, f, g);
+    if (r == 0 && q.strip_flux) add_strip_flux<R>(c, k, q.x, g);
+  };
+
+  const int ys = D > 0 ? y0 : y1 - 1;
+  const int ye = D > 0 ? y1 : y0 - 1;
+  R c1f[kQ], c1g[kQ], n1f[kQ], n1g[kQ], a1f[3], a1g[3];  // level-1 window
+  R c2f[kQ], c2g[kQ], n2f[kQ], n2g[kQ], a2f[3], a2g[3];  // level-2 window
+  R c3f[kQ], c3g[kQ], n3f[kQ], n3g[kQ], a3f[3], a3g[3];  // level-3 window
+  // prologue: level 1 of rows ys-3D .. ys+2D, level 2 of ys-2D .. ys+D,
+  // level 3 of ys-D and ys; rows alternate between the two buffers
+  issue(ys - 3 * D, 0);
+  issue(ys - 2 * D, 1);
+  wait_vm();
+  level1(ys - 3 * D, 0, c1f, c1g);
+  wait_lgkm();
+  issue(ys - D, 0);
+  level1(ys - 2 * D, 1, n1f, n1g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  wait_lgkm();
+  issue(ys, 1);
+  level1(ys - D, 0, n1f, n1g);
+  next_level(ys - 2 * D, c1f, c1g, n1f, n1g, a1f, a1g, c2f, c2g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  wait_lgkm();
+  issue(ys + D, 0);
+  level1(ys, 1, n1f, n1g);
+  next_level(ys - D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+  slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  wait_lgkm();
+  issue(ys + 2 * D, 1);
+  level1(ys + D, 0, n1f, n1g);
+  next_level(ys, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+  next_level(ys - D, c2f, c2g, n2f, n2g, a2f, a2g, c3f, c3g);
+  slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  wait_lgkm();
+  issue(ys + 3 * D, 0);
+  level1(ys + 2 * D, 1, n1f, n1g);
+  next_level(ys + D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+  next_level(ys, c2f, c2g, n2f, n2g, a2f, a2g, n3f, n3g);
+  slide<D>(a3f, a3g, c3f, c3g, n3f, n3g);
+  slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
+  slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  wait_vm();
+  int b = 0;
+  for (int y = ys; y != ye; y += D, b ^= 1) {
+    // row y+3D is in buffer b; buffer b^1 (row y+2D) has been read
+    wait_lgkm();
+    if (y + D != ye) issue(y + 4 * D, b ^ 1);
+    level1(y + 3 * D, b, n1f, n1g);
+    next_level(y + 2 * D, c1f, c1g, n1f, n1g, a1f, a1g, n2f, n2g);
+    next_level(y + D, c2f, c2g, n2f, n2g, a2f, a2g, n3f, n3g);
+    R pf[kQ], pg[kQ];
+    second_collide<R, D, WALLS, MODEL>(c, k, q, y, c3f, c3g, n3f, n3g, a3f, a3g, pf, pg);
+    wait_vm();
+    emit<S, R, WALLS>(c, k, B, q, y, pf, pg);
+    slide<D>(a3f, a3g, c3f, c3g, n3f, n3g);
+    slide<D>(a2f, a2g, c2f, c2g, n2f, n2g);
+    slide<D>(a1f, a1g, c1f, c1g, n1f, n1g);
+  }
+}
+
+template <typename S, typename R, int MODEL>
+__global__ __launch_bounds__(kWave)
+__attribute__((amdgpu_waves_per_eu(2))) void k_step4(CavDev c, int strips_x, int nseg, int seg_rows,
+                                                     int order) {
+  __shared__ S lds[2 * kPlanes * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = tile_of(blockIdx.x, gridDim.x, order & 1, (order & 2) && (c.parity & 1));
+  if (w >= strips_x * nseg) return;  // uniform per wavefront; no barriers follow
+  const int strip = w % strips_x, seg = w / strips_x;
+  const int x0 = strip * kStrip4Cols;
+  const int y0 = seg * seg_rows;
+  const int y1 = min(y0 + seg_rows, c.ny);
+  const Col q = make_col<3>(c, x0 - 3 + lane, lane, y0);
+  const Coef<R> k(c);
+  const S *__restrict__ A = static_cast<const S *>(c.parity ? c.pop[1] : c.pop[0]);
+  S *__restrict__ B = static_cast<S *>(c.parity ? c.pop[0] : c.pop[1]);
+  const bool down = (order & 4) && (seg & 1);
+  const bool inner = interior_segment<3>(c, x0, y0, y1);
+  if (down) {
+    if (inner)
+      walk4_staged<S, R, -1, false, MODEL>(c, k, A, B, q, y0, y1, x0, lds);
+    else
+      walk4_staged<S, R, -1, true, MODEL>(c, k, A, B, q, y0, y1, x0, lds);
+  } else {
+    if (inner)
+      walk4_staged<S, R, +1, false, MODEL>(c, k, A, B, q, y0, y1, x0, lds);
+    else
+      walk4_staged<S, R, +1, true, MODEL>(c, k, A, B, q, y0, y1, x0, lds);
+  }
+}
+
+hipError_t dispatch4(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
+  if (cfg.seg4 < 1 || cfg.seg4 > kMaxSegmentRows) return hipErrorInvalidValue;
+  const int strips_x = (c.nx + kStrip4Cols - 1) / kStrip4Cols;
+  const int nseg = (c.ny + cfg.seg4 - 1) / cfg.seg4;
+  const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
+  with_model(c.solid_model, [&](auto m) {
+    hipLaunchKernelGGL((k_step4<float, float, decltype(m)::value>), dim3(strips_x * nseg), dim3(kWave), 0, s,
+                       c, strips_x, nseg, cfg.seg4, order);
+    return 0;
+  });
+  return hipGetLastError();
+}
+
 // The same three-step walk with the level-2 window kept in LDS instead of
 // registers, for FP64, whose two register windows exceed the register file.
 // Rows are loaded directly (the LDS holds the window, not staged rows).  The
@@ -994,6 +1141,10 @@ hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev
                                                           cfg, launch_index, grid, err_dev, s)
                         : dispatch3_batch<float, float>(cavs_dev, items_dev, hdr_dev, item_cap, model,
                                                         cfg, launch_index, grid, err_dev, s);
+}
+
+hipError_t launch_step4(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {
+  return precision == 0 ? hipErrorInvalidValue : dispatch4(c, cfg, s);
 }
 
 hipError_t launch_step3(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {

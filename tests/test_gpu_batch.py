@@ -155,30 +155,38 @@ def test_fused_batch_uneven_steps_equal_solo(P, fuse, flags, seg, chunk):
         assert_matches_oracle(c, *states[k], n, got[k][0])
 
 
-def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path, prec):
     import json
     path = str(tmp_path / "tune.json")
-    case = dict(cavity(200, 90, Ra=1e6, heater_center=0.4), pattern=P.LBM_PATTERN_AB)
+    case = dict(cavity(200, 90, Ra=1e6, heater_center=0.4), pattern=P.LBM_PATTERN_AB, precision=prec)
     f0, g0 = _random_state(81, 200, 90)
-    print("case autotune 200x90 FP64", flush=True)
+    print(f"case autotune 200x90 precision {prec}", flush=True)
     with P.Context(device=0, max_slots=2) as ctx:
-        ctx.autotune(0, 200, 90, path)
-        bx, by, cpl, flags = ctx.get_launch(0)
-        fuse, seg = ctx.get_fusion(0)
-        assert bx % 64 == 0 and bx * by <= 256 and cpl in (1, 2, 4) and fuse in (2, 3) and 1 <= seg <= 12
+        ctx.autotune(prec, 200, 90, path)
+        bx, by, cpl, flags = ctx.get_launch(prec)
+        fuse, seg = ctx.get_fusion(prec)
+        assert bx % 64 == 0 and bx * by <= 256 and cpl in (1, 2, 4) and 1 <= seg <= 12
+        assert fuse in ((2, 3) if prec == 0 else (2, 3, 4))
         assert flags & P.LBM_LAUNCH_ZIGZAG
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)
         ctx.step(s, 9)
         tuned = ctx.state_save(s)
     entry = list(json.load(open(path)).values())
-    assert len(entry) == 1 and len(entry[0]) == 9 and entry[0][:4] == [bx, by, cpl, flags]
+    assert len(entry) == 1 and len(entry[0]) == (9 if prec == 0 else 11) and entry[0][:4] == [bx, by, cpl, flags]
     e = entry[0]
-    assert fuse == (3 if e[8] / 3 < e[6] / 2 else 2) and seg == (e[7] if fuse == 3 else e[5])
+    per = {2: e[6] / 2, 3: e[8] / 3}
+    if prec == 1:
+        per[4] = e[10] / 4
+    want = 3 if per[3] < per[2] else 2
+    if prec == 1 and per[4] < per[want]:
+        want = 4
+    assert fuse == want and seg == {2: e[5], 3: e[7], 4: e[9] if prec == 1 else None}[fuse]
     with P.Context(device=0, max_slots=2) as ctx:
-        ctx.autotune(0, 200, 90, path)  # reuses the cached entry
-        assert ctx.get_launch(0) == (bx, by, cpl, flags) and ctx.get_fusion(0) == (fuse, seg)
-        ctx.set_fusion(0, 1)
+        ctx.autotune(prec, 200, 90, path)  # reuses the cached entry
+        assert ctx.get_launch(prec) == (bx, by, cpl, flags) and ctx.get_fusion(prec) == (fuse, seg)
+        ctx.set_fusion(prec, 1)
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)
         ctx.step(s, 9)

@@ -25,16 +25,16 @@ def P():
 FL_LINF = 1e-3
 
 
-@pytest.mark.parametrize("pattern", [0, 1], ids=["in_place", "three_step"])
+@pytest.mark.parametrize("pattern,fuse", [(0, 1), (1, 3), (1, 4)], ids=["in_place", "three_step", "four_step"])
 @pytest.mark.parametrize("variant", ["literal", "eq6"])
-def test_fp32_shifted_small_cavity_to_20k_steps(P, variant, pattern):
+def test_fp32_shifted_small_cavity_to_20k_steps(P, variant, pattern, fuse):
     case = dict(small_cavity(variant), precision=P.LBM_FP32_SHIFTED, pattern=pattern)
-    print(f"case small_cavity[{variant}] FP32 shifted pattern {pattern} to 20000 steps", flush=True)
+    print(f"case small_cavity[{variant}] FP32 shifted pattern {pattern} fuse {fuse} to 20000 steps", flush=True)
     o = oracle.Oracle(oracle.case_from_dict(case)).init_solid()
     rows = []
     with P.Context(device=0, max_slots=2) as ctx:
         if pattern == 1:
-            ctx.set_fusion(P.LBM_FP32_SHIFTED, 3, 6)
+            ctx.set_fusion(P.LBM_FP32_SHIFTED, fuse, 6)
         s = ctx.add(case)
         done = 0
         for t in (5000, 10000, 20000):
@@ -73,22 +73,23 @@ def test_fp32_shifted_short_run_tracks_oracle(P):
     assert np.max(np.abs(gg - go)) <= 2e-6
 
 
-def test_fp32_fused_full_size_tracks_oracle(P):
-    """The FP32-shifted variant at the benchmark's size and launch
-    configuration (2048x1024, two lattices, three steps per launch, default
-    segments) from a random state, against the FP64 oracle."""
+@pytest.mark.parametrize("fuse", [3, 4])
+def test_fp32_fused_full_size_tracks_oracle(P, fuse):
+    """The FP32-shifted variant at the benchmark's size (2048x1024, two
+    lattices, three or four steps per launch, 6-row segments) from a random
+    state, 12 steps, against the FP64 oracle."""
     from btrirt_workloads import large_cavity
     case = dict(large_cavity(), precision=P.LBM_FP32_SHIFTED, pattern=P.LBM_PATTERN_AB)
     f0, g0 = _random_state(29, 2048, 1024)
-    print("case 2048x1024 FP32 three-step, 6 steps vs oracle", flush=True)
+    print(f"case 2048x1024 FP32 {fuse} steps per launch, 12 steps vs oracle", flush=True)
     with P.Context(device=0, max_slots=1) as ctx:
-        assert ctx.get_fusion(1) == (3, 6)
+        ctx.set_fusion(1, fuse, 6)
         s = ctx.add(case)
         ctx.state_load(s, f0, g0)
-        ctx.step(s, 6)
+        ctx.step(s, 12)
         fg, gg = ctx.state_save(s)
         st = ctx.reduce(s)
-    o = oracle.Oracle(oracle.case_from_dict(case)).set_populations(f0, g0).step(6)
+    o = oracle.Oracle(oracle.case_from_dict(case)).set_populations(f0, g0).step(12)
     fo, go = o.populations()
     assert np.max(np.abs(fg - fo)) <= 2e-6
     assert np.max(np.abs(gg - go)) <= 2e-6

@@ -323,8 +323,11 @@ def test_fused_kernels_equal_single_steps(P, geom, prec, seg, steps):
     out = []
     # single steps, two-step launches with the zigzag segment walk (default)
     # and with every segment walked upwards, rows loaded directly or staged
-    for fuse, flags in ((1, P.LBM_LAUNCH_DEFAULT), (2, P.LBM_LAUNCH_DEFAULT), (2, 5), (2, 5 | P.LBM_LAUNCH_STAGED),
-                        (2, 13 | P.LBM_LAUNCH_STAGED), (3, P.LBM_LAUNCH_DEFAULT), (3, 5 | P.LBM_LAUNCH_STAGED)):
+    modes = [(1, P.LBM_LAUNCH_DEFAULT), (2, P.LBM_LAUNCH_DEFAULT), (2, 5), (2, 5 | P.LBM_LAUNCH_STAGED),
+             (2, 13 | P.LBM_LAUNCH_STAGED), (3, P.LBM_LAUNCH_DEFAULT), (3, 5 | P.LBM_LAUNCH_STAGED)]
+    if prec == 1:  # four steps per launch (FP32), zigzag and upward walks
+        modes += [(4, P.LBM_LAUNCH_DEFAULT), (4, 5 | P.LBM_LAUNCH_STAGED)]
+    for fuse, flags in modes:
         with P.Context(device=0, max_slots=1) as ctx:
             ctx.set_fusion(prec, fuse, seg)
             ctx.set_launch(prec, 256, 1, 1, flags)
@@ -388,13 +391,14 @@ def test_fused_kernels_full_size_match_oracle(P):
 
 def test_default_fusion_follows_cavity_size(P):
     """The default fusion adapts to the cavity (FP64 below 2^20 cells: two
-    steps per launch; three-step segments shrink until a launch has at least
-    1024 wavefronts); an explicit setting is used as given.  The adapted
+    steps per launch; FP32 from 2^21 cells: four; three-step segments shrink
+    until a launch has at least 1024 wavefronts); an explicit setting is used
+    as given.  The adapted
     launches equal single steps bit for bit."""
     print("case default fusion per cavity size", flush=True)
-    cases = [((2048, 1024, 0), (3, 6)), ((1024, 512, 0), (2, 2)), ((2048, 1024, 1), (3, 6)),
-             ((1024, 512, 1), (3, 6)), ((768, 384, 1), (3, 4)), ((512, 256, 1), (3, 2)),
-             ((128, 64, 1), (3, 1))]
+    cases = [((2048, 1024, 0), (3, 6)), ((1024, 512, 0), (2, 2)), ((2048, 1024, 1), (4, 6)),
+             ((1536, 768, 1), (3, 6)), ((1024, 512, 1), (3, 6)), ((768, 384, 1), (3, 4)),
+             ((512, 256, 1), (3, 2)), ((128, 64, 1), (3, 1))]
     with P.Context(device=0, max_slots=len(cases) + 1) as ctx:
         for (nx, ny, prec), want in cases:
             s = ctx.add(dict(cavity(nx, ny), precision=prec, pattern=P.LBM_PATTERN_AB))
@@ -406,6 +410,12 @@ def test_default_fusion_follows_cavity_size(P):
         ctx.set_fusion(0, 3, 6)
         s = ctx.add(dict(cavity(256, 128), pattern=P.LBM_PATTERN_AB))
         assert ctx.slot_fusion(s) == (3, 6) and ctx.get_fusion(0) == (3, 6)
+        # four steps per launch are FP32 only
+        with pytest.raises(P.LbmError) as ei:
+            ctx.set_fusion(0, 4)
+        assert ei.value.code == P.LBM_EINVAL
+        ctx.set_fusion(1, 4, 5)
+        assert ctx.get_fusion(1) == (4, 5)
     # adapted three-step launches of a small FP32 cavity (1-row segments)
     case = dict(cavity(128, 64, heater_center=0.4), precision=P.LBM_FP32_SHIFTED, pattern=P.LBM_PATTERN_AB)
     f0, g0 = _random_state(57, 128, 64)
