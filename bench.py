@@ -213,7 +213,7 @@ def fp32_variant(P, steps, path="ab"):
     per = fuse if path != "aa" else 1
     # bytes a launch must move (144 B per cell) over the time of one launch
     gbs = BYTES_PER_LU[1] * cells / (ms / steps * per * 1e-3) / 1e9
-    return dict(mlups=round(mlups, 1), ms_per_step=ms / steps, pattern=pattern, steps_per_launch=per,
+    return dict(mlups=round(mlups, 1), ms_per_step=round(ms / steps, 5), pattern=pattern, steps_per_launch=per,
                 achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
                 effective_gbs=round(BYTES_PER_LU[1] * cells * steps / (ms * 1e-3) / 1e9, 1),
                 melt_fraction=st["melt_fraction"])
