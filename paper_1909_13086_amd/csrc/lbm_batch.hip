@@ -54,7 +54,9 @@ hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
                              int32_t *err_dev, hipStream_t s) {
   const int by = 256 / tile_bx;
   const dim3 block(tile_bx, by < 1 ? 1 : by);
-  with_model(model, [&](auto m) {
+  // the one-step tiles keep the general collision for every kernel variant
+  // (dropping the (1 - k0) p term measured no faster here)
+  with_model(model == kScaleUnitK0 ? kSolidScale : model, [&](auto m) {
     constexpr int M = decltype(m)::value;
     if (precision == 0)
       hipLaunchKernelGGL((k_step_batch<double, double, M>), dim3(grid), block, 0, s, cavs_dev,

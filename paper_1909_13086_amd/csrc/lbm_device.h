@@ -142,16 +142,26 @@ struct Moments {
 // 3 w c_i.v, are v_x/3, v_y/3 on the axes and (+/-v_x/3 + v_y/3)/4 on the
 // diagonals.  Each pair is relaxed as soon as its two terms exist, so few
 // temporaries are live at once.
-template <typename R>
+// With k0 = 1 (UNIT) the (1 - k0) p term is dropped.
+template <typename R, bool UNIT>
 __device__ __forceinline__ void relax_pair(R &pp, R &pm, R omk0, R E, R O) {
-  pp = omk0 * pp + (E + O);
-  pm = omk0 * pm + (E - O);
+  if constexpr (UNIT) {
+    pp = E + O;
+    pm = E - O;
+  } else {
+    pp = omk0 * pp + (E + O);
+    pm = omk0 * pm + (E - O);
+  }
 }
 
 // One B-TriRT collision of a cell, shifted populations in place.  MODEL is
-// the solid-phase treatment of the flow (kSolid*), fixed at compile time.
+// the kernel variant: the solid-phase treatment of the flow (kSolid*), or
+// kScaleUnitK0 (the scaled-velocity treatment with k0 = 1 for f and g),
+// fixed at compile time.
 template <typename R, int MODEL>
 __device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ]) {
+  constexpr int SOLID = MODEL == kScaleUnitK0 ? kSolidScale : MODEL;
+  constexpr bool UNIT = MODEL == kScaleUnitK0;
   constexpr R third = R(1.0 / 3.0);
   // (a) total enthalpy (the other moments of g are taken in (e), so that
   // they are not held through the flow part)
@@ -165,7 +175,7 @@ __device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ
   const Moments<R> mf(f);
   const R Fb = k.gbc * Cpth;  // buoyancy rho0 g beta theta, along +y
   R ux, uy, rux, ruy, Fx = R(0), Fy = Fb;
-  if constexpr (MODEL == kSolidDarcy) {
+  if constexpr (SOLID == kSolidDarcy) {
     // rho0 u = j + (Fb - A rho0 u)/2, A = C (1 - fl)^2 / (fl^3 + eps): with
     // D = fl^3 + eps + C (1 - fl)^2 / 2, u = (fl^3 + eps)/D (j + Fb/2)/rho0
     // and the drag -A rho0 u = -C (1 - fl)^2 / D (j + Fb/2)
@@ -184,8 +194,8 @@ __device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ
   } else {
     // rho0 u = j + F/2, scaled by the liquid fraction (or free: bounce-back model)
     const R qy = mf.jy + R(0.5) * Fb;
-    rux = MODEL == kSolidPbb ? mf.jx : fl * mf.jx;
-    ruy = MODEL == kSolidPbb ? qy : fl * qy;
+    rux = SOLID == kSolidPbb ? mf.jx : fl * mf.jx;
+    ruy = SOLID == kSolidPbb ? qy : fl * qy;
     ux = k.inv_rho0 * rux;
     uy = k.inv_rho0 * ruy;
   }
@@ -195,7 +205,7 @@ __device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ
   // (Pi the second moment); the odd parts need k0 rho0 u - a1
   // = k1 rho0 u - (k1 - k0) j + (1 - k1/2) F.
   {
-    constexpr bool fx = MODEL == kSolidDarcy;  // the force has an x part only under the drag
+    constexpr bool fx = SOLID == kSolidDarcy;  // the force has an x part only under the drag
     const R rxx = rux * ux, ryy = ruy * uy;
     const R r3 = mf.m0 * third;
     const R hF = k.hk2f3 * Fy;
@@ -213,17 +223,17 @@ __device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ
     const R t36 = R(0.25) * b9 - R(0.5) * tr6;
     const R rcu2 = (rux + ruy) * (ux + uy), rcu3 = (ruy - rux) * (uy - ux);
     R pre[kQ];
-    if constexpr (MODEL == kSolidPbb) {
+    if constexpr (SOLID == kSolidPbb) {
 #pragma unroll
       for (int i = 0; i < kQ; ++i) pre[i] = f[i];
     }
-    relax_pair<R>(f[1], f[3], k.omk0f, k.k0h * rxx + ((b9 - R(2) * a6xx) + a6yy), vx3);
-    relax_pair<R>(f[2], f[4], k.omk0f, k.k0h * ryy + ((b9 - R(2) * a6yy) + a6xx), vy3);
-    relax_pair<R>(f[5], f[7], k.omk0f, k.k0e * rcu2 + (t36 - R(1.5) * a6xy), R(0.25) * (vx3 + vy3));
-    relax_pair<R>(f[6], f[8], k.omk0f, k.k0e * rcu3 + (t36 + R(1.5) * a6xy), R(0.25) * (vy3 - vx3));
+    relax_pair<R, UNIT>(f[1], f[3], k.omk0f, k.k0h * rxx + ((b9 - R(2) * a6xx) + a6yy), vx3);
+    relax_pair<R, UNIT>(f[2], f[4], k.omk0f, k.k0h * ryy + ((b9 - R(2) * a6yy) + a6xx), vy3);
+    relax_pair<R, UNIT>(f[5], f[7], k.omk0f, k.k0e * rcu2 + (t36 - R(1.5) * a6xy), R(0.25) * (vx3 + vy3));
+    relax_pair<R, UNIT>(f[6], f[8], k.omk0f, k.k0e * rcu3 + (t36 + R(1.5) * a6xy), R(0.25) * (vy3 - vx3));
     // rest population: k0 w0 X - (9/2) w0 Q_0:a2 = 4 (k0 X/9) + 4 (a2xx + a2yy)/6
-    const R f0 = k.omk0f * f[0] + R(4) * (b9 + tr6);
-    if constexpr (MODEL == kSolidPbb) {
+    const R f0 = UNIT ? R(4) * (b9 + tr6) : k.omk0f * f[0] + R(4) * (b9 + tr6);
+    if constexpr (SOLID == kSolidPbb) {
       // partial bounce-back: each member mixes its post-collision value with
       // its partner's pre-collision one, weighted by the solid fraction
       const R ns = R(1) - fl;
@@ -252,11 +262,12 @@ __device__ __forceinline__ void collide(const Rates<R> &k, R (&f)[kQ], R (&g)[kQ
     const R tr6 = a6xx + a6yy;
     const R t36 = R(0.25) * b9 - R(0.5) * tr6;
     // rest population: k0 (dH - (5/9) Cp theta) + 4 (a2xx + a2yy)/6
-    const R g0 = k.omk0g * g[0] + ((k.k0g * dH - R(5) * b9) + R(4) * tr6);
-    relax_pair<R>(g[1], g[3], k.omk0g, (b9 - R(2) * a6xx) + a6yy, vx3);
-    relax_pair<R>(g[2], g[4], k.omk0g, (b9 - R(2) * a6yy) + a6xx, vy3);
-    relax_pair<R>(g[5], g[7], k.omk0g, t36 - R(1.5) * a6xy, R(0.25) * (vx3 + vy3));
-    relax_pair<R>(g[6], g[8], k.omk0g, t36 + R(1.5) * a6xy, R(0.25) * (vy3 - vx3));
+    const R g0 = UNIT ? (k.k0g * dH - R(5) * b9) + R(4) * tr6
+                     : k.omk0g * g[0] + ((k.k0g * dH - R(5) * b9) + R(4) * tr6);
+    relax_pair<R, UNIT>(g[1], g[3], k.omk0g, (b9 - R(2) * a6xx) + a6yy, vx3);
+    relax_pair<R, UNIT>(g[2], g[4], k.omk0g, (b9 - R(2) * a6yy) + a6xx, vy3);
+    relax_pair<R, UNIT>(g[5], g[7], k.omk0g, t36 - R(1.5) * a6xy, R(0.25) * (vx3 + vy3));
+    relax_pair<R, UNIT>(g[6], g[8], k.omk0g, t36 + R(1.5) * a6xy, R(0.25) * (vy3 - vx3));
     g[0] = g0;
   }
 }
@@ -433,6 +444,13 @@ __host__ __device__ inline auto with_model(int model, Fn &&fn) {
     case kSolidPbb: return fn(std::integral_constant<int, kSolidPbb>{});
     default: return fn(std::integral_constant<int, kSolidScale>{});
   }
+}
+
+// The same for a kernel variant (CavDev::kmodel), kScaleUnitK0 included.
+template <typename Fn>
+__host__ __device__ inline auto with_kernel_model(int kmodel, Fn &&fn) {
+  if (kmodel == kScaleUnitK0) return fn(std::integral_constant<int, kScaleUnitK0>{});
+  return with_model(kmodel, static_cast<Fn &&>(fn));
 }
 
 __device__ __forceinline__ int storage_mode(const CavDev &c) {

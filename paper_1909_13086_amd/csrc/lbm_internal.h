@@ -15,6 +15,14 @@ constexpr int kWave = 64;
 constexpr int kXcds = 8;
 // How the solid holds the flow still (values of LBM_SOLID_* in lbm.h).
 constexpr int kSolidScale = 0, kSolidDarcy = 1, kSolidPbb = 2;
+// Kernel variants of the fused and batched kernels: the three solid models,
+// and the scaled-velocity model with k0 = 1 for both populations, where the
+// (1 - k0) p term of Eq. (2) vanishes, so the collision skips it and the
+// pre-collision populations are dead once their moments are taken.  Its
+// results equal the general collision's with those rates (a multiply by an
+// exact zero dropped; only the sign of a zero sum can differ).
+constexpr int kScaleUnitK0 = 3;
+constexpr int kKernelModels = 4;
 
 // The rates of Eq. (2) and the constants of one cavity in the combinations
 // that the collision multiplies by (its pair form, lbm_device.h), in the
@@ -48,6 +56,7 @@ struct CavDev {
   int32_t pattern;     // 0 in place (A-A), 1 two lattices
   int32_t active_steps; // batched launch: launches of the current chunk that advance it
   int32_t solid_model;  // LBM_SOLID_*
+  int32_t kmodel;       // kernel variant: solid_model, or kScaleUnitK0 (set_rates)
   int64_t plane;       // elements between consecutive population planes of a cell
   // relaxation rates of Eq. (2)
   double k0g, k1g, k2g, k0f, k1f, k2f;
@@ -96,10 +105,14 @@ inline Rates<R> make_rates(const CavDev &c) {
   return k;
 }
 
-// Fills the rate tables of a descriptor whose other fields are set.
+// Fills the rate tables and the kernel variant of a descriptor whose other
+// fields are set.
 inline void set_rates(CavDev &c) {
   c.r64 = make_rates<double>(c);
   c.r32 = make_rates<float>(c);
+  const bool unit_k0 = c.k0g == 1.0 && c.k0f == 1.0 && c.r64.omk0g == 0.0 && c.r64.omk0f == 0.0 &&
+                       c.r32.omk0g == 0.0f && c.r32.omk0f == 0.0f;
+  c.kmodel = c.solid_model == kSolidScale && unit_k0 ? kScaleUnitK0 : c.solid_model;
 }
 
 // Batched launch: tiles of many cavities in one grid.
@@ -180,7 +193,7 @@ hipError_t launch_step4(const CavDev &c, int precision, const LaunchCfg &cfg, hi
 // hdr_dev: {first tile, tile count} of this launch; tiles_dev holds tile_cap
 // entries.  A header that is empty or points outside them advances nothing
 // and sets *err_dev to kErrBatchHeader, which the host reports as an error.
-// model: the solid model shared by every cavity of the tile list (kSolid*).
+// model: the kernel variant shared by every cavity of the list (CavDev::kmodel).
 hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
                              const int32_t *hdr_dev, int tile_cap, int precision, int model,
                              int tile_bx, int tile_rows, int launch_index, int grid,

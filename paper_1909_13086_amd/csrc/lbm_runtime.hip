@@ -613,9 +613,11 @@ constexpr int kBatchTileRows = 16;
 constexpr int kStrip2Cols = lbm::kStripCols;
 
 // Launches of a cache group come per precision, kind (one-step tiles, two-
-// or three-step segments) and solid model; each has a {first, count} header.
-constexpr int kLaunchKinds = 2 * 3 * 3;
-int launch_bit(int prec, int kind, int model) { return (prec * 3 + kind) * 3 + model; }
+// or three-step segments) and kernel variant (solid model, or the scaled
+// model with k0 = 1: CavDev::kmodel); each has a {first, count} header.
+constexpr int kLaunchKinds = 2 * 3 * lbm::kKernelModels;
+static_assert(kLaunchKinds <= 31, "launch kinds are bits of an int");
+int launch_bit(int prec, int kind, int model) { return (prec * 3 + kind) * lbm::kKernelModels + model; }
 // kind of a slot's batched launches: its steps per launch - 1 (batched
 // launches fuse at most three steps; a four-step slot takes three there)
 int batch_kind(const lbm_ctx *c, const Slot &s) { return std::min(steps_per_launch(c, s), 3) - 1; }
@@ -685,7 +687,7 @@ int rebuild_batch(lbm_ctx *c) {
   for (int g = 0; g < ngroups; ++g)
     for (int prec = 0; prec < 2; ++prec)
       for (int kind = 1; kind < 3; ++kind)
-        for (int model = 0; model < 3; ++model) {
+        for (int model = 0; model < lbm::kKernelModels; ++model) {
           const LaunchCfg &L = c->launch[prec];
           int best = kind == 2 ? L.seg3 : L.seg;
           if (L.adapt) {
@@ -695,7 +697,7 @@ int rebuild_batch(lbm_ctx *c) {
               for (size_t j = 0; j < ncav; ++j) {
                 const Slot &s = c->slots[b.members[j]];
                 if (group_of[j] == g && s.cs.precision == prec && batch_kind(c, s) == kind &&
-                    s.cs.solid_model == model)
+                    s.dev.kmodel == model)
                   items += segs_of(s, cols_of(kind), seg);
               }
               if (items == 0) break;
@@ -720,7 +722,7 @@ int rebuild_batch(lbm_ctx *c) {
                 ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
     else
       ntiles += (size_t)segs_of(s, cols_of(kind),
-                                b.hdr_seg[hdr_index(group_of[j], s.cs.precision, kind, s.cs.solid_model) / 2]);
+                                b.hdr_seg[hdr_index(group_of[j], s.cs.precision, kind, s.dev.kmodel) / 2]);
   }
   const size_t nhdr = (size_t)std::max(ngroups, 1) * kLaunchKinds * 2;
   HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
@@ -742,12 +744,12 @@ int rebuild_batch(lbm_ctx *c) {
   for (int g = 0; g < ngroups; ++g) {
     for (int prec = 0; prec < 2; ++prec) {
       for (int kind = 0; kind < 3; ++kind) {
-        for (int model = 0; model < 3; ++model) {
+        for (int model = 0; model < lbm::kKernelModels; ++model) {
           const size_t first = t;
           for (size_t j = 0; j < ncav; ++j) {
             if (group_of[j] != g) continue;
             const Slot &s = c->slots[b.members[j]];
-            if (s.cs.precision != prec || batch_kind(c, s) != kind || s.cs.solid_model != model)
+            if (s.cs.precision != prec || batch_kind(c, s) != kind || s.dev.kmodel != model)
               continue;
             if (kind == 0) {
               for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
@@ -801,7 +803,7 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
   for (int g = 0; g < (int)b.group_precs.size() && err == hipSuccess; ++g) {
     for (int k = 0; k < chunk && err == hipSuccess; ++k)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-        for (int model = 0; model < 3 && err == hipSuccess; ++model)
+        for (int model = 0; model < lbm::kKernelModels && err == hipSuccess; ++model)
           if (b.group_precs[g] & (1 << launch_bit(prec, 0, model)))
             err = lbm::launch_step_batch(b.cavs_dev, b.tiles_dev,
                                          b.hdr_dev + hdr_index(g, prec, 0, model), (int)b.tile_cap,
@@ -809,7 +811,7 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
                                          batch_grid(c), c->err_dev, c->stream);
     for (int j = 0; j < (chunk + 1) / 2 && err == hipSuccess; ++j)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-        for (int model = 0; model < 3 && err == hipSuccess; ++model)
+        for (int model = 0; model < lbm::kKernelModels && err == hipSuccess; ++model)
           if (b.group_precs[g] & (1 << launch_bit(prec, 1, model))) {
             LaunchCfg L = c->launch[prec];
             L.seg = b.hdr_seg[hdr_index(g, prec, 1, model) / 2];
@@ -820,7 +822,7 @@ hipError_t enqueue_batch_chunk(lbm_ctx *c, int chunk) {
           }
     for (int j = 0; j < (chunk + 2) / 3 && err == hipSuccess; ++j)
       for (int prec = 0; prec < 2 && err == hipSuccess; ++prec)
-        for (int model = 0; model < 3 && err == hipSuccess; ++model)
+        for (int model = 0; model < lbm::kKernelModels && err == hipSuccess; ++model)
           if (b.group_precs[g] & (1 << launch_bit(prec, 2, model))) {
             LaunchCfg L = c->launch[prec];
             L.seg3 = b.hdr_seg[hdr_index(g, prec, 2, model) / 2];

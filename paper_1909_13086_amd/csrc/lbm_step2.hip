@@ -519,7 +519,7 @@ hipError_t dispatch(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int per_block = STAGED ? kStagedWaves : kDirectWaves;
   const dim3 grid((waves + per_block - 1) / per_block);
   const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
-  with_model(c.solid_model, [&](auto m) {
+  with_kernel_model(c.kmodel, [&](auto m) {
     hipLaunchKernelGGL((k_step2<S, R, STAGED, decltype(m)::value>), grid, dim3(per_block * kWave), 0,
                        s, c, strips_x, nseg, cfg.seg, order);
     return 0;
@@ -761,7 +761,7 @@ hipError_t dispatch4(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int strips_x = (c.nx + kStrip4Cols - 1) / kStrip4Cols;
   const int nseg = (c.ny + cfg.seg4 - 1) / cfg.seg4;
   const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
-  with_model(c.solid_model, [&](auto m) {
+  with_kernel_model(c.kmodel, [&](auto m) {
     hipLaunchKernelGGL((k_step4<float, float, decltype(m)::value>), dim3(strips_x * nseg), dim3(kWave), 0, s,
                        c, strips_x, nseg, cfg.seg4, order);
     return 0;
@@ -948,7 +948,7 @@ hipError_t dispatch3(const CavDev &c, const LaunchCfg &cfg, hipStream_t s) {
   const int waves = strips_x * nseg;
   const dim3 grid((waves + kStep3Waves - 1) / kStep3Waves);
   const int order = (cfg.xcd ? 1 : 0) | (cfg.reverse ? 2 : 0) | (cfg.zigzag ? 4 : 0);
-  with_model(c.solid_model, [&](auto m) {
+  with_kernel_model(c.kmodel, [&](auto m) {
     hipLaunchKernelGGL((k_step3<S, R, decltype(m)::value>), grid, dim3(kStep3Waves * kWave), 0, s, c,
                        strips_x, nseg, cfg.seg3, order);
     return 0;
@@ -1085,7 +1085,7 @@ hipError_t dispatch3_batch(const CavDev *cavs, const BatchTile *items, const int
                            hipStream_t s) {
   if (cfg.seg3 < 1 || cfg.seg3 > kMaxSegmentRows) return hipErrorInvalidValue;
   const int order = cfg.zigzag ? 4 : 0;
-  with_model(model, [&](auto m) {
+  with_kernel_model(model, [&](auto m) {
     hipLaunchKernelGGL((k_step3_batch<S, R, decltype(m)::value>), dim3(grid), dim3(kStagedWaves * kWave), 0,
                        s, cavs, items, hdr, item_cap, cfg.seg3, launch_index, order, err);
     return 0;
@@ -1100,7 +1100,7 @@ hipError_t dispatch_batch(const CavDev *cavs, const BatchTile *items, const int3
   if (cfg.seg < 1 || cfg.seg > kMaxSegmentRows) return hipErrorInvalidValue;
   const int per_block = STAGED ? kStagedWaves : kDirectWaves;
   const int order = cfg.zigzag ? 4 : 0;
-  with_model(model, [&](auto m) {
+  with_kernel_model(model, [&](auto m) {
     hipLaunchKernelGGL((k_step2_batch<S, R, STAGED, decltype(m)::value>), dim3(grid),
                        dim3(per_block * kWave), 0, s, cavs, items, hdr, item_cap, cfg.seg,
                        launch_index, order, err);

@@ -309,16 +309,25 @@ def test_checkpoint_resume_is_bitwise(P, pattern, prec):
 FUSED_GEOMS = GEOMS + [(130, 70, 0, 0, 0.4, 0.3), (200, 37, 1, 1, 0.5, 0.25), (63, 17, 1, 0, 0.6, 0.5)]
 
 
+# free rates of both populations: all distinct, and k0 = 1 for f and g, for
+# which the fused kernels drop the (1 - k0) p term of Eq. (2) while the
+# single-step kernel keeps it
+FUSED_RATES = {"general": dict(k0_g=0.9, k2_g=1.2, k0_f=1.1, k1_f=0.85),
+               "unit_k0": dict(k0_g=1.0, k2_g=1.2, k0_f=1.0, k1_f=0.85)}
+
+
+@pytest.mark.parametrize("rates", sorted(FUSED_RATES))
 @pytest.mark.parametrize("geom", FUSED_GEOMS, ids=[f"{g[0]}x{g[1]}p{g[2]}{g[3]}" for g in FUSED_GEOMS])
 @pytest.mark.parametrize("prec,seg,steps", [(0, 8, 2), (0, 16, 7), (1, 32, 6), (0, 32, 13), (1, 8, 5),
                                              (0, 6, 4), (1, 5, 3), (0, 1, 2), (0, 3, 5), (1, 64, 4)])
-def test_fused_kernels_equal_single_steps(P, geom, prec, seg, steps):
+def test_fused_kernels_equal_single_steps(P, geom, prec, seg, steps, rates):
     nx, ny, px, py, hc, hw = geom
     case = dict(cavity(nx, ny, periodic_x=px, periodic_y=py, heater_center=hc, heater_width=hw,
                        param_mode=1, nu=0.04, alpha=0.06, gbeta=3e-3, latent=0.8, Tm=0.1, Th=0.9,
-                       k0_g=0.9, k2_g=1.2, k0_f=1.1, k1_f=0.85),
+                       **FUSED_RATES[rates]),
                 precision=prec, pattern=P.LBM_PATTERN_AB)
-    print(f"case two-step {nx}x{ny} periodic=({px},{py}) prec={prec} seg={seg} steps={steps}", flush=True)
+    print(f"case two-step {nx}x{ny} periodic=({px},{py}) prec={prec} seg={seg} steps={steps} rates={rates}",
+          flush=True)
     f0, g0 = _random_state(2000 + nx + ny, nx, ny)
     out = []
     # single steps, two-step launches with the zigzag segment walk (default)
