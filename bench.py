@@ -38,10 +38,10 @@ REPORT_EVERY = 100
 # traffic), counter summary, steps per launch
 CSRC = os.path.join(ROOT, "paper_1909_13086_amd", "csrc")
 PATHS = {
-    "ab": dict(kernel="k_step3<double,double,0>", src=("lbm_internal.h", "lbm_device.h", "lbm_step2.hip"),
+    "ab": dict(kernel="k_step3<double,double,3>", src=("lbm_internal.h", "lbm_device.h", "lbm_step2.hip"),
                traffic=os.path.join(ROOT, "profiles", "traffic_k_step3_fp64_2048x1024.md"), per_launch=3,
                pattern="two lattices, three steps per launch, level-2 window in LDS"),
-    "ab2": dict(kernel="k_step2<double,double,true,0>", src=("lbm_internal.h", "lbm_device.h", "lbm_step2.hip"),
+    "ab2": dict(kernel="k_step2<double,double,true,3>", src=("lbm_internal.h", "lbm_device.h", "lbm_step2.hip"),
                 traffic=os.path.join(ROOT, "profiles", "traffic_k_step2_fp64_2048x1024.md"), per_launch=2,
                 pattern="two lattices, two steps per launch, rows staged through LDS"),
     "aa": dict(kernel="k_step<double,double,1,false,0,SM> (SM = 0, 1: even and odd A-A steps)",
