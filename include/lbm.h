@@ -287,13 +287,16 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * that are not a multiple end with shorter launches.  Batched launches
  * (lbm_step_many) fuse as many steps as the slot's single-cavity launches.
  * Results equal those of single steps bit for bit.  Default: 3 steps per
- * launch in segments of 6 rows; two-step segments of 2 rows (FP64) or 4
- * rows (FP32).  Until lbm_set_fusion or lbm_autotune
- * sets it, the default follows each cavity's size: FP64 cavities below 2^20
- * cells take two steps per launch, FP32 cavities of 2^21 cells or more take
- * four, three- and four-step segments shrink to 4, 2 or 1 rows until a
- * launch has at least 1024 wavefronts (lbm_slot_fusion shows the result), and batched launches choose their segment rows per cache
- * group so that the group's segments fill the device's wavefronts evenly;
+ * launch in segments of 4 rows (FP64) or 6 rows (FP32), four-step segments
+ * of 6 rows; two-step segments of 2 rows (FP64) or 4 rows (FP32).  Until
+ * lbm_set_fusion or lbm_autotune sets it, the default follows each cavity's
+ * size: FP64 cavities below 2^18 cells take two steps per launch, FP32
+ * cavities of 2^21 cells or more take four; when some segment length of 1,
+ * 2, 3, 4, 6 or 8 rows lets every wavefront of the launch be resident on
+ * the device at once, the rows are those minimising resident passes x rows
+ * collided per segment, else the default rows stand (lbm_slot_fusion shows
+ * the result).  Batched launches choose their segment rows per cache group
+ * so that the group's segments fill the device's wavefronts evenly;
  * lbm_get_fusion returns the nominal values.  LBM_EINVAL for
  * steps_per_launch outside 1..4 (4 with LBM_FP64) or segment_rows outside
  * 0..64. */

@@ -141,14 +141,14 @@ constexpr int kStrip3Cols = kWave - 4;  // owned columns of a three-step wavefro
 constexpr int kStrip4Cols = kWave - 6;  // owned columns of a four-step wavefront
 
 // Defaults per precision, the fastest measured on MI355X at 2048x1024 and
-// 4096x2048: three steps per launch in segments of 6 rows; two-step launches
-// (the batched path, shorter remainders) in segments of 2 rows (FP64) or 4
-// rows (FP32).
+// 4096x2048: three steps per launch in segments of 4 rows (FP64) or 6 rows
+// (FP32), four-step segments of 6 rows; two-step launches (the batched path,
+// shorter remainders) in segments of 2 rows (FP64) or 4 rows (FP32).
 inline LaunchCfg default_launch(int precision) {
   LaunchCfg L;
   L.fuse = 3;
   L.seg = precision == 0 ? 2 : 4;
-  L.seg3 = 6;
+  L.seg3 = precision == 0 ? 4 : 6;
   return L;
 }
 
@@ -216,6 +216,10 @@ hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev
                               hipStream_t s);
 // Workgroups of a batched two- or three-step launch that fill the device once.
 int step2_batch_grid(int num_cus);
+// Wavefronts of a single-cavity launch fusing `steps` (2, 3 or 4) steps that
+// one CU holds at once, from the occupancy of the kernel instance for that
+// precision, kernel variant and (two steps) row staging; 0 if unknown.
+int fused_waves_per_cu(int precision, int steps, int kmodel, bool staged);
 hipError_t launch_reduce(const CavDev &c, int precision, double *partials, StatsDev *out,
                          hipStream_t s);
 hipError_t launch_fields(const CavDev &c, int precision, uint32_t mask, double *out,

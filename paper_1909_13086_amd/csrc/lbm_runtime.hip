@@ -289,6 +289,9 @@ struct lbm_ctx {
   LaunchCfg launch[2] = {lbm::default_launch(0), lbm::default_launch(1)};
   int graph_chunk = 0;
   int num_cus = 256;
+  // resident wavefronts per CU of the fused single-cavity kernels, per
+  // [precision][steps per launch][kernel variant][rows staged] (lbm_create)
+  int fused_wpc[2][5][lbm::kKernelModels][2] = {};
   size_t group_bytes = size_t(160) << 20;  // cache-group capacity of the batched launch
   Batch batch;
 };
@@ -451,35 +454,49 @@ int enqueue_one_step(lbm_ctx *c, Slot &s) {
   return LBM_OK;
 }
 
-// Launch configuration of a slot.  While the fusion is the default (not set
-// by lbm_set_fusion or lbm_autotune) it follows the cavity size, as measured
-// on MI355X: FP64 cavities below 2^20 cells take two steps per launch (the
-// three-step kernel wins only on larger ones), FP32 cavities of 2^21 cells
-// or more take four (below, where the lattices sit in the Infinity Cache,
-// three are faster), and three- and four-step segments shrink (6, 4, 2, 1
-// rows) until the launch has at least 1024 wavefronts, so small cavities
-// still fill the GPU.
+// Segment rows of a single-cavity launch fusing `steps` steps over strips of
+// the given count, under the default fusion.  When some length lets every
+// wavefront of the launch be resident at once (`slots` of them: one pass),
+// the rows minimise passes x rows collided per segment (steps x rows stored
+// plus steps (steps - 1) halo rows): short segments fill the launch of a
+// small cavity, and a one-pass length spares a larger one an idle tail pass.
+// Otherwise (many passes) the configured rows stand, which measured best on
+// the large cavities.
+int pick_rows(int64_t strips, int ny, int steps, int rows, int64_t slots) {
+  if (slots <= 0) return rows;
+  int best = rows;
+  int64_t best_cost = INT64_MAX;
+  bool one_pass = false;
+  for (int r : {1, 2, 3, 4, 6, 8}) {
+    const int64_t passes = (strips * ((ny + r - 1) / r) + slots - 1) / slots;
+    one_pass = one_pass || passes == 1;
+    const int64_t cost = passes * (steps * r + steps * (steps - 1));
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = r;
+    }
+  }
+  return one_pass ? best : rows;
+}
+
+// The launch configuration of one slot.  Unless the context's fusion is set
+// explicitly (by lbm_set_fusion or lbm_autotune) it follows the cavity size,
+// as measured on MI355X: FP64 cavities below 2^18 cells take two steps per
+// launch (the three-step kernel wins only on larger ones), FP32 cavities of
+// 2^21 cells or more take four (below, where the lattices sit in the
+// Infinity Cache, three are faster), and the segment rows follow pick_rows
+// with the resident wavefronts of the kernel the launch uses.
 LaunchCfg slot_launch(const lbm_ctx *c, const Slot &s) {
   LaunchCfg L = c->launch[s.cs.precision];
   if (!L.adapt || s.cs.pattern != LBM_PATTERN_AB) return L;
-  if (L.fuse == 3 && s.cs.precision == LBM_FP64 && (int64_t)s.cs.nx * s.cs.ny < (int64_t)1 << 20) L.fuse = 2;
-  if (L.fuse == 3 && s.cs.precision == LBM_FP32_SHIFTED && (int64_t)s.cs.nx * s.cs.ny >= (int64_t)1 << 21)
-    L.fuse = 4;
-  if (L.fuse == 3) {
-    const int64_t strips = (s.cs.nx + lbm::kStrip3Cols - 1) / lbm::kStrip3Cols;
-    for (int seg : {6, 4, 2, 1}) {
-      if (seg > L.seg3) continue;
-      L.seg3 = seg;
-      if (strips * ((s.cs.ny + seg - 1) / seg) >= 1024) break;
-    }
-  }
-  if (L.fuse == 4) {
-    const int64_t strips = (s.cs.nx + lbm::kStrip4Cols - 1) / lbm::kStrip4Cols;
-    for (int seg : {6, 4, 2, 1}) {
-      if (seg > L.seg4) continue;
-      L.seg4 = seg;
-      if (strips * ((s.cs.ny + seg - 1) / seg) >= 1024) break;
-    }
+  const int64_t cells = (int64_t)s.cs.nx * s.cs.ny;
+  if (L.fuse == 3 && s.cs.precision == LBM_FP64 && cells < (int64_t)1 << 18) L.fuse = 2;
+  if (L.fuse == 3 && s.cs.precision == LBM_FP32_SHIFTED && cells >= (int64_t)1 << 21) L.fuse = 4;
+  if (L.fuse >= 2) {
+    const int cols = L.fuse == 2 ? lbm::kStripCols : (L.fuse == 3 ? lbm::kStrip3Cols : lbm::kStrip4Cols);
+    int &rows = L.fuse == 2 ? L.seg : (L.fuse == 3 ? L.seg3 : L.seg4);
+    const int wpc = c->fused_wpc[s.cs.precision][L.fuse][s.dev.kmodel][L.staged ? 1 : 0];
+    rows = pick_rows((s.cs.nx + cols - 1) / cols, s.cs.ny, L.fuse, rows, (int64_t)wpc * c->num_cus);
   }
   return L;
 }
@@ -994,6 +1011,11 @@ int lbm_create(lbm_ctx **out, int device, void *hip_stream, size_t hbm_budget, i
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
+  for (int prec = 0; prec < 2; ++prec)
+    for (int steps = 2; steps <= 4; ++steps)
+      for (int km = 0; km < lbm::kKernelModels; ++km)
+        for (int staged = 0; staged < 2; ++staged)
+          c->fused_wpc[prec][steps][km][staged] = lbm::fused_waves_per_cu(prec, steps, km, staged != 0);
   int rc = LBM_OK;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);

@@ -1143,6 +1143,41 @@ hipError_t launch_step3_batch(const CavDev *cavs_dev, const BatchTile *items_dev
                                                         cfg, launch_index, grid, err_dev, s);
 }
 
+namespace {
+
+template <typename K>
+int resident_waves(K kernel, int block_waves) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(kernel),
+                                                   block_waves * kWave, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return blocks * block_waves;
+}
+
+template <typename S, typename R>
+int fused_waves(int steps, int kmodel, bool staged) {
+  return with_kernel_model(kmodel, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    if (steps == 2)
+      return staged ? resident_waves(&k_step2<S, R, true, M>, kStagedWaves)
+                    : resident_waves(&k_step2<S, R, false, M>, kDirectWaves);
+    if (steps == 3) return resident_waves(&k_step3<S, R, M>, kStep3Waves);
+    if constexpr (sizeof(R) == 4) {
+      if (steps == 4) return resident_waves(&k_step4<S, R, M>, 1);
+    }
+    return 0;
+  });
+}
+
+}  // namespace
+
+int fused_waves_per_cu(int precision, int steps, int kmodel, bool staged) {
+  return precision == 0 ? fused_waves<double, double>(steps, kmodel, staged)
+                        : fused_waves<float, float>(steps, kmodel, staged);
+}
+
 hipError_t launch_step4(const CavDev &c, int precision, const LaunchCfg &cfg, hipStream_t s) {
   return precision == 0 ? hipErrorInvalidValue : dispatch4(c, cfg, s);
 }

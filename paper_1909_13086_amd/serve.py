@@ -150,7 +150,7 @@ def bench_serving(P, n=48, rate=20.0, steps_lo=1000, steps_hi=5000, budget=16 <<
     ctx.close()
     out = dict(requests=n, arrival_rate_per_s=rate, steps_range=[steps_lo, steps_hi], budget_bytes=budget,
                pattern="in place" if pattern == P.LBM_PATTERN_AA else
-               "two lattices, fused launches (three steps; two for FP64 cavities below 2^20 cells, "
+               "two lattices, fused launches (three steps; two for FP64 cavities below 2^18 cells, "
                "four for FP32 cavities from 2^21 cells)",
                p50_s=round(s["p50_s"], 4), p99_s=round(s["p99_s"], 4), mean_s=round(s["mean_s"], 4),
                mlups=round(s["mlups"], 1), makespan_s=round(s["makespan_s"], 3),

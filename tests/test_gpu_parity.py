@@ -374,7 +374,7 @@ def test_fused_kernels_in_graphs_and_with_reports(P, chunk):
 
 def test_fused_kernels_full_size_match_oracle(P):
     """The benchmark's FP64 workload in its launch configuration (three steps
-    per launch, 6-row segments) and with two steps per launch, 6 steps from a
+    per launch, 4-row segments) and with two steps per launch, 6 steps from a
     random state, against the oracle."""
     case = dict(large_cavity(), pattern=P.LBM_PATTERN_AB)
     print("case 2048x1024 FP64 fused kernels, 6 steps vs oracle", flush=True)
@@ -383,7 +383,7 @@ def test_fused_kernels_full_size_match_oracle(P):
     for fuse in (3, 2):
         with P.Context(device=0, max_slots=1) as ctx:  # default launch configuration
             if fuse == 3:
-                assert ctx.get_fusion(0) == (3, 6)
+                assert ctx.get_fusion(0) == (3, 4)
                 assert ctx.get_launch(0)[3] == P.LBM_LAUNCH_DEFAULT
             else:
                 ctx.set_fusion(0, 2)
@@ -399,15 +399,19 @@ def test_fused_kernels_full_size_match_oracle(P):
 
 
 def test_default_fusion_follows_cavity_size(P):
-    """The default fusion adapts to the cavity (FP64 below 2^20 cells: two
-    steps per launch; FP32 from 2^21 cells: four; three-step segments shrink
-    until a launch has at least 1024 wavefronts); an explicit setting is used
-    as given.  The adapted
-    launches equal single steps bit for bit."""
+    """The default fusion adapts to the cavity (FP64 below 2^18 cells: two
+    steps per launch; FP32 from 2^21 cells: four; segment rows minimising
+    resident passes x rows collided when some length fits the launch in one
+    pass, else 4 rows for FP64 three steps and 6 for FP32); an explicit
+    setting is used as given.  The expected rows follow from the resident
+    wavefronts of these kernels on MI355X (FP64 two and three steps and FP32
+    four steps: 8 per CU; FP32 three steps: 12).  The adapted launches equal
+    single steps bit for bit."""
     print("case default fusion per cavity size", flush=True)
-    cases = [((2048, 1024, 0), (3, 6)), ((1024, 512, 0), (2, 2)), ((2048, 1024, 1), (4, 6)),
-             ((1536, 768, 1), (3, 6)), ((1024, 512, 1), (3, 6)), ((768, 384, 1), (3, 4)),
-             ((512, 256, 1), (3, 2)), ((128, 64, 1), (3, 1))]
+    cases = [((2048, 1024, 0), (3, 4)), ((1536, 768, 0), (3, 4)), ((1024, 512, 0), (3, 6)),
+             ((768, 384, 0), (3, 3)), ((512, 256, 0), (2, 2)), ((128, 64, 0), (2, 1)),
+             ((2048, 1024, 1), (4, 6)), ((1536, 768, 1), (3, 8)), ((1024, 512, 1), (3, 4)),
+             ((768, 384, 1), (3, 2)), ((512, 256, 1), (3, 1)), ((128, 64, 1), (3, 1))]
     with P.Context(device=0, max_slots=len(cases) + 1) as ctx:
         for (nx, ny, prec), want in cases:
             s = ctx.add(dict(cavity(nx, ny), precision=prec, pattern=P.LBM_PATTERN_AB))
