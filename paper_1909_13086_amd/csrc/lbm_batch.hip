@@ -55,7 +55,8 @@ hipError_t launch_step_batch(const CavDev *cavs_dev, const BatchTile *tiles_dev,
   const int by = 256 / tile_bx;
   const dim3 block(tile_bx, by < 1 ? 1 : by);
   // the one-step tiles keep the general collision for every kernel variant
-  // (dropping the (1 - k0) p term measured no faster here)
+  // (dropping the (1 - k0) p term measured no faster here); the host groups
+  // their unit-k0 cavities with the scaled model's
   with_model(model == kScaleUnitK0 ? kSolidScale : model, [&](auto m) {
     constexpr int M = decltype(m)::value;
     if (precision == 0)

@@ -638,6 +638,12 @@ int launch_bit(int prec, int kind, int model) { return (prec * 3 + kind) * lbm::
 // kind of a slot's batched launches: its steps per launch - 1 (batched
 // launches fuse at most three steps; a four-step slot takes three there)
 int batch_kind(const lbm_ctx *c, const Slot &s) { return std::min(steps_per_launch(c, s), 3) - 1; }
+// kernel variant a slot's batched launches of the given kind use: the
+// one-step tiles keep the general collision, so their unit-k0 cavities share
+// the launch of the scaled model
+int batch_model(const Slot &s, int kind) {
+  return kind == 0 && s.dev.kmodel == lbm::kScaleUnitK0 ? lbm::kSolidScale : s.dev.kmodel;
+}
 int hdr_index(int g, int prec, int kind, int model) {
   return (g * kLaunchKinds + launch_bit(prec, kind, model)) * 2;
 }
@@ -714,7 +720,7 @@ int rebuild_batch(lbm_ctx *c) {
               for (size_t j = 0; j < ncav; ++j) {
                 const Slot &s = c->slots[b.members[j]];
                 if (group_of[j] == g && s.cs.precision == prec && batch_kind(c, s) == kind &&
-                    s.dev.kmodel == model)
+                    batch_model(s, kind) == model)
                   items += segs_of(s, cols_of(kind), seg);
               }
               if (items == 0) break;
@@ -739,7 +745,7 @@ int rebuild_batch(lbm_ctx *c) {
                 ((s.cs.ny + kBatchTileRows - 1) / kBatchTileRows);
     else
       ntiles += (size_t)segs_of(s, cols_of(kind),
-                                b.hdr_seg[hdr_index(group_of[j], s.cs.precision, kind, s.dev.kmodel) / 2]);
+                                b.hdr_seg[hdr_index(group_of[j], s.cs.precision, kind, batch_model(s, kind)) / 2]);
   }
   const size_t nhdr = (size_t)std::max(ngroups, 1) * kLaunchKinds * 2;
   HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers may feed an earlier copy
@@ -766,7 +772,7 @@ int rebuild_batch(lbm_ctx *c) {
           for (size_t j = 0; j < ncav; ++j) {
             if (group_of[j] != g) continue;
             const Slot &s = c->slots[b.members[j]];
-            if (s.cs.precision != prec || batch_kind(c, s) != kind || s.dev.kmodel != model)
+            if (s.cs.precision != prec || batch_kind(c, s) != kind || batch_model(s, kind) != model)
               continue;
             if (kind == 0) {
               for (int y0 = 0; y0 < s.cs.ny; y0 += kBatchTileRows)
