@@ -294,7 +294,8 @@ int lbm_get_launch(lbm_ctx *c, int precision, int *bx, int *by, int *cpl, int *f
  * cavities of 2^21 cells or more take four; when some segment length of 1,
  * 2, 3, 4, 6 or 8 rows lets every wavefront of the launch be resident on
  * the device at once, the rows are those minimising resident passes x rows
- * collided per segment, else the default rows stand (lbm_slot_fusion shows
+ * collided per segment x max(rho, resident wavefronts per SIMD), rho = 4
+ * (FP64) or 1.5 (FP32), else the default rows stand (lbm_slot_fusion shows
  * the result).  Batched launches choose their segment rows per cache group
  * so that the group's segments fill the device's wavefronts evenly;
  * lbm_get_fusion returns the nominal values.  LBM_EINVAL for

@@ -457,20 +457,26 @@ int enqueue_one_step(lbm_ctx *c, Slot &s) {
 // Segment rows of a single-cavity launch fusing `steps` steps over strips of
 // the given count, under the default fusion.  When some length lets every
 // wavefront of the launch be resident at once (`slots` of them: one pass),
-// the rows minimise passes x rows collided per segment (steps x rows stored
-// plus steps (steps - 1) halo rows): short segments fill the launch of a
-// small cavity, and a one-pass length spares a larger one an idle tail pass.
+// the rows minimise the modelled time
+//   passes x rows collided per segment x max(rho, resident waves per SIMD),
+// rows collided being steps x rows stored plus steps (steps - 1) halo rows:
+// a wavefront's walk costs its rows either in latency (rho, the latency of a
+// row over its arithmetic on one SIMD) or, with more waves per SIMD than
+// that, in shared arithmetic.  Short segments so fill the launch of a small
+// cavity, and a one-pass length spares a larger one an idle tail pass.
 // Otherwise (many passes) the configured rows stand, which measured best on
 // the large cavities.
-int pick_rows(int64_t strips, int ny, int steps, int rows, int64_t slots) {
-  if (slots <= 0) return rows;
+int pick_rows(int64_t strips, int ny, int steps, int rows, int64_t slots, int64_t simds, double rho) {
+  if (slots <= 0 || simds <= 0) return rows;
   int best = rows;
-  int64_t best_cost = INT64_MAX;
+  double best_cost = 1e300;
   bool one_pass = false;
   for (int r : {1, 2, 3, 4, 6, 8}) {
-    const int64_t passes = (strips * ((ny + r - 1) / r) + slots - 1) / slots;
+    const int64_t waves = strips * ((ny + r - 1) / r);
+    const int64_t passes = (waves + slots - 1) / slots;
     one_pass = one_pass || passes == 1;
-    const int64_t cost = passes * (steps * r + steps * (steps - 1));
+    const double per_simd = (double)std::min(waves, slots) / (double)simds;
+    const double cost = (double)passes * (steps * r + steps * (steps - 1)) * std::max(rho, per_simd);
     if (cost < best_cost) {
       best_cost = cost;
       best = r;
@@ -496,7 +502,12 @@ LaunchCfg slot_launch(const lbm_ctx *c, const Slot &s) {
     const int cols = L.fuse == 2 ? lbm::kStripCols : (L.fuse == 3 ? lbm::kStrip3Cols : lbm::kStrip4Cols);
     int &rows = L.fuse == 2 ? L.seg : (L.fuse == 3 ? L.seg3 : L.seg4);
     const int wpc = c->fused_wpc[s.cs.precision][L.fuse][s.dev.kmodel][L.staged ? 1 : 0];
-    rows = pick_rows((s.cs.nx + cols - 1) / cols, s.cs.ny, L.fuse, rows, (int64_t)wpc * c->num_cus);
+    // rho as fitted on MI355X: the FP64 walks are bound by row latency at any
+    // residency they reach (2 waves per SIMD), the FP32 ones, whose rows carry
+    // the same arithmetic on half the bytes, by arithmetic above 1.5 waves
+    const double rho = s.cs.precision == LBM_FP64 ? 4.0 : 1.5;
+    rows = pick_rows((s.cs.nx + cols - 1) / cols, s.cs.ny, L.fuse, rows, (int64_t)wpc * c->num_cus,
+                     (int64_t)4 * c->num_cus /* four SIMDs per CU */, rho);
   }
   return L;
 }

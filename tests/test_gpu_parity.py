@@ -401,8 +401,9 @@ def test_fused_kernels_full_size_match_oracle(P):
 def test_default_fusion_follows_cavity_size(P):
     """The default fusion adapts to the cavity (FP64 below 2^18 cells: two
     steps per launch; FP32 from 2^21 cells: four; segment rows minimising
-    resident passes x rows collided when some length fits the launch in one
-    pass, else 4 rows for FP64 three steps and 6 for FP32); an explicit
+    resident passes x rows collided x max(rho, waves per SIMD) when some
+    length fits the launch in one pass, else 4 rows for FP64 three steps
+    and 6 for FP32); an explicit
     setting is used as given.  The expected rows follow from the resident
     wavefronts of these kernels on MI355X (FP64 two and three steps and FP32
     four steps: 8 per CU; FP32 three steps: 12).  The adapted launches equal
@@ -410,8 +411,8 @@ def test_default_fusion_follows_cavity_size(P):
     print("case default fusion per cavity size", flush=True)
     cases = [((2048, 1024, 0), (3, 4)), ((1536, 768, 0), (3, 4)), ((1024, 512, 0), (3, 6)),
              ((768, 384, 0), (3, 3)), ((512, 256, 0), (2, 2)), ((128, 64, 0), (2, 1)),
-             ((2048, 1024, 1), (4, 6)), ((1536, 768, 1), (3, 8)), ((1024, 512, 1), (3, 4)),
-             ((768, 384, 1), (3, 2)), ((512, 256, 1), (3, 1)), ((128, 64, 1), (3, 1))]
+             ((2048, 1024, 1), (4, 6)), ((1536, 768, 1), (3, 8)), ((1024, 512, 1), (3, 6)),
+             ((768, 384, 1), (3, 3)), ((512, 256, 1), (3, 2)), ((128, 64, 1), (3, 1))]
     with P.Context(device=0, max_slots=len(cases) + 1) as ctx:
         for (nx, ny, prec), want in cases:
             s = ctx.add(dict(cavity(nx, ny), precision=prec, pattern=P.LBM_PATTERN_AB))
