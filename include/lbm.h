@@ -190,7 +190,7 @@ int lbm_step(lbm_ctx *c, int slot, int64_t nsteps);
  * requests of different lengths share the device (continuous batching).
  * Asynchronous.  Each result equals that of lbm_step on the slot alone. */
 int lbm_step_many(lbm_ctx *c, int count, const int32_t *slots, const int64_t *nsteps);
-/* Capacity of one cache group of the batched launch (default 160 MiB): within
+/* Capacity of one cache group of the batched launch (default 192 MiB): within
  * a chunk of graph-replayed steps, each group of cavities whose footprints
  * sum to at most this advances through all its steps before the next group,
  * so its populations stay in the last-level cache.  A cavity whose footprint

@@ -292,7 +292,7 @@ struct lbm_ctx {
   // resident wavefronts per CU of the fused single-cavity kernels, per
   // [precision][steps per launch][kernel variant][rows staged] (lbm_create)
   int fused_wpc[2][5][lbm::kKernelModels][2] = {};
-  size_t group_bytes = size_t(160) << 20;  // cache-group capacity of the batched launch
+  size_t group_bytes = size_t(192) << 20;  // cache-group capacity of the batched launch
   Batch batch;
 };
 

@@ -197,7 +197,7 @@ def test_autotune_choice_is_valid_cached_and_exact(P, tmp_path, prec):
 @pytest.mark.parametrize("pattern", ["aa", "ab"])
 def test_full_batch_sweep_equals_solo_runs(P, pattern):
     """The 64-cavity workload in the launch configuration the benchmark times
-    (FP32 shifted, 100-step graphs, cache groups of at most 160 MiB): every
+    (FP32 shifted, 100-step graphs, cache groups of at most 192 MiB): every
     cavity's diagnostics equal its solo run's bit for bit after a graph chunk
     and an odd remainder."""
     pat = P.LBM_PATTERN_AA if pattern == "aa" else P.LBM_PATTERN_AB
