@@ -543,7 +543,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving runs (about two minutes)")
     ap.add_argument("--calib-copy", type=int, default=0, help="run only a copy of this many bytes")
     ap.add_argument("--only", choices=["fp32", "batched", "batched_two_step", "serving", "serving_two_step",
-                                       "serving_study", "sizes"],
+                                       "serving_study", "sizes", "small_solve"],
                     default="",
                     help="run one variant alone (for profiling) and print its result")
     ap.add_argument("--study", choices=["heater", "solid"], default="",
@@ -575,6 +575,8 @@ def main():
             res = batched_variant(P, args.steps, pattern=P.LBM_PATTERN_AB)
         elif args.only == "sizes":
             res = fused_sizes_variant(P, args.steps)
+        elif args.only == "small_solve":
+            res = small_cavity_solves(P)
         elif args.only == "serving_study":
             res = serving_study(P, P.LBM_PATTERN_AA if args.path == "aa" else P.LBM_PATTERN_AB)
         elif args.only == "serving_two_step":
