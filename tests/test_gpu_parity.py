@@ -443,3 +443,31 @@ def test_default_fusion_follows_cavity_size(P):
             ctx.step(s, 14)
             out.append(ctx.state_save(s))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("nx,ny,prec,want", [(768, 384, 0, (3, 3)), (1024, 512, 0, (3, 6)),
+                                             (512, 256, 0, (2, 2)), (768, 384, 1, (3, 3)),
+                                             (1536, 768, 1, (3, 8)), (2048, 1024, 1, (4, 6))],
+                         ids=["fp64_768", "fp64_1024", "fp64_512", "fp32_768", "fp32_1536", "fp32_2048"])
+def test_adapted_fusion_equals_single_steps(P, nx, ny, prec, want):
+    """The launches the size rule chooses at real sizes (three steps in 3-,
+    6- and 8-row segments, two steps, four steps) advance a random state
+    exactly as single two-lattice steps do, with a remainder launch."""
+    print(f"case adapted fusion {nx}x{ny} precision {prec}", flush=True)
+    case = dict(cavity(nx, ny, Ra=1e6, heater_center=0.35), precision=prec, pattern=P.LBM_PATTERN_AB)
+    f0, g0 = _random_state(90 + nx, nx, ny)
+    out = []
+    for fuse in (None, 1):
+        with P.Context(device=0, max_slots=1) as ctx:
+            if fuse:
+                ctx.set_fusion(prec, fuse)
+            s = ctx.add(case)
+            if fuse is None:
+                assert ctx.slot_fusion(s) == want
+            ctx.state_load(s, f0, g0)
+            ctx.step(s, 14)
+            out.append((ctx.state_save(s), ctx.reduce(s)))
+    (a, sa), (b, sb) = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for k in ("melt_fraction", "total_H", "heat_in_cum", "budget_residual"):
+        assert sa[k] == sb[k], k
